@@ -1,0 +1,169 @@
+"""FP64 CPU oracle of the uplink receive path -- TEST INFRASTRUCTURE ONLY.
+
+The arithmetic lives in ``rx_oracle.c`` (plain C, FP64, radix-2 FFT); this
+module builds it with gcc and wraps it with ctypes.  Only the test suite, the
+smoke check and the CPU-baseline leg of the benchmark may import it.  It
+shares no code with the GPU library in ``paper_1901_07499_amd``.
+
+Per-function citations to the paper are in the C source header.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rx_oracle.c")
+LIB_PATH = os.environ.get("RX_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
+
+MRC, ZF = 0, 1
+
+
+def build(force: bool = True) -> str:
+    """Compile ``liboracle.so`` next to the source (plain -O2, no fast-math, no FMA contraction)."""
+    if os.environ.get("RX_ORACLE_LIB"):
+        return LIB_PATH       # a prebuilt variant supplied by the mutation tests
+    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-std=c11", "-O2", "-fPIC", "-shared", "-ffp-contract=off",
+                               "-fno-fast-math", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm", "-lpthread"])
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("n_ant", ctypes.c_int32), ("fft_len", ctypes.c_int32), ("cp_len", ctypes.c_int32),
+                ("n_used", ctypes.c_int32), ("n_sym", ctypes.c_int32), ("bits_per_sym", ctypes.c_int32),
+                ("combiner", ctypes.c_int32), ("pilot", ctypes.POINTER(ctypes.c_double))]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.environ.get("RX_ORACLE_LIB") and (
+                not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(_SRC)):
+            build(force=True)
+        lib = ctypes.CDLL(LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        u8p = ctypes.POINTER(ctypes.c_uint8)
+        for name, src in (("oracle_process_frame", ctypes.POINTER(ctypes.c_int16)),
+                          ("oracle_process_frame_f64", dp)):
+            f = getattr(lib, name)
+            f.argtypes = [ctypes.POINTER(_Params), src, ctypes.c_int64, dp, dp, dp, u8p, ctypes.c_int]
+            f.restype = ctypes.c_int
+        lib.oracle_fft_symbols.argtypes = [ctypes.POINTER(_Params), ctypes.POINTER(ctypes.c_int16),
+                                           ctypes.c_int64, dp]
+        lib.oracle_fft_symbols.restype = ctypes.c_int
+        lib.oracle_fft_interleaved.argtypes = [dp, ctypes.c_int]
+        lib.oracle_fft_interleaved.restype = ctypes.c_int
+        lib.oracle_demap.argtypes = [dp, ctypes.c_int64, ctypes.c_int, u8p]
+        lib.oracle_demap.restype = ctypes.c_int
+        lib.oracle_subcarrier_map.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int32)]
+        lib.oracle_subcarrier_map.restype = None
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: Optional[np.ndarray], ct):
+    return None if a is None else a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def fft(x: np.ndarray) -> np.ndarray:
+    """Unnormalised forward FFT of a complex vector (radix-2 DIT, FP64)."""
+    x = np.ascontiguousarray(x, dtype=np.complex128)
+    buf = np.ascontiguousarray(x.view(np.float64)).copy()
+    r = _load().oracle_fft_interleaved(_ptr(buf, ctypes.c_double), x.size)
+    if r:
+        raise ValueError("FFT length must be a power of two")
+    return buf.view(np.complex128)
+
+
+def subcarrier_map(fft_len: int, n_used: int) -> np.ndarray:
+    out = np.empty(n_used, dtype=np.int32)
+    _load().oracle_subcarrier_map(fft_len, n_used, _ptr(out, ctypes.c_int32))
+    return out
+
+
+def demap(xhat: np.ndarray, bits_per_sym: int) -> np.ndarray:
+    """Hard decisions of complex symbols -> bit values [..., b] in {0, 1}."""
+    x = np.ascontiguousarray(xhat, dtype=np.complex128)
+    out = np.empty(x.shape + (bits_per_sym,), dtype=np.uint8)
+    r = _load().oracle_demap(_ptr(x.view(np.float64), ctypes.c_double), x.size, bits_per_sym,
+                             _ptr(out, ctypes.c_uint8))
+    if r:
+        raise ValueError("bits_per_sym must be 2, 4 or 6")
+    return out
+
+
+class Result:
+    """Oracle outputs of one run: H [S][A][U], g [S][U], xhat [S][T-1][U] (complex128), bits."""
+
+    def __init__(self, H, g, xhat, bits):
+        self.H, self.g, self.xhat, self.bits = H, g, xhat, bits
+
+
+def _params(n_ant, fft_len, cp_len, n_used, n_sym, bits_per_sym, combiner, pilot):
+    pil = np.ascontiguousarray(np.asarray(pilot, dtype=np.complex128)).view(np.float64)
+    p = _Params(n_ant, fft_len, cp_len, n_used, n_sym, bits_per_sym, combiner, _ptr(pil, ctypes.c_double))
+    return p, pil
+
+
+def process_frame(iq: np.ndarray, pilot: np.ndarray, *, n_ant: int, fft_len: int, cp_len: int,
+                  n_used: int, n_sym: int, bits_per_sym: int, combiner: int = MRC,
+                  n_threads: int = 1, f64: bool = False) -> Result:
+    """Run the oracle on ``iq`` (int16 [S][T][A][CP+N][2]) or, with ``f64``, on complex
+    samples (complex128 [S][T][A][CP+N])."""
+    p, keep = _params(n_ant, fft_len, cp_len, n_used, n_sym, bits_per_sym, combiner, pilot)
+    S = iq.shape[0]
+    H = np.empty((S, n_ant, n_used), dtype=np.complex128)
+    g = np.empty((S, n_used), dtype=np.float64)
+    xhat = np.empty((S, n_sym - 1, n_used), dtype=np.complex128)
+    bits = np.empty((S, n_sym - 1, n_used * bits_per_sym // 8), dtype=np.uint8)
+    lib = _load()
+    if f64:
+        src = np.ascontiguousarray(iq, dtype=np.complex128)
+        r = lib.oracle_process_frame_f64(ctypes.byref(p), _ptr(src.view(np.float64), ctypes.c_double), S,
+                                         _ptr(H.view(np.float64), ctypes.c_double), _ptr(g, ctypes.c_double),
+                                         _ptr(xhat.view(np.float64), ctypes.c_double),
+                                         _ptr(bits, ctypes.c_uint8), n_threads)
+    else:
+        src = np.ascontiguousarray(iq, dtype=np.int16)
+        r = lib.oracle_process_frame(ctypes.byref(p), _ptr(src, ctypes.c_int16), S,
+                                     _ptr(H.view(np.float64), ctypes.c_double), _ptr(g, ctypes.c_double),
+                                     _ptr(xhat.view(np.float64), ctypes.c_double),
+                                     _ptr(bits, ctypes.c_uint8), n_threads)
+    del keep
+    if r:
+        raise ValueError(f"oracle rejected the parameters or failed (status {r})")
+    return Result(H, g, xhat, bits)
+
+
+def fft_symbols(iq: np.ndarray, pilot: np.ndarray, *, n_ant: int, fft_len: int, cp_len: int,
+                n_used: int, n_sym: int, bits_per_sym: int) -> np.ndarray:
+    """CP removal + FFT of every symbol: complex128 [S][T][A][N]."""
+    p, keep = _params(n_ant, fft_len, cp_len, n_used, n_sym, bits_per_sym, MRC, pilot)
+    S = iq.shape[0]
+    out = np.empty((S, n_sym, n_ant, fft_len), dtype=np.complex128)
+    src = np.ascontiguousarray(iq, dtype=np.int16)
+    r = _load().oracle_fft_symbols(ctypes.byref(p), _ptr(src, ctypes.c_int16), S,
+                                   _ptr(out.view(np.float64), ctypes.c_double))
+    del keep
+    if r:
+        raise ValueError(f"oracle rejected the parameters (status {r})")
+    return out
+
+
+def run_config(frames, combiner: int = MRC, n_threads: int = 1, slots=None) -> Result:
+    """Oracle over a ``rxgen.Frames`` object (optionally a slice of slots)."""
+    c = frames.cfg
+    iq = frames.iq if slots is None else frames.iq[slots]
+    return process_frame(iq, frames.pilot, n_ant=c.n_ant, fft_len=c.fft_len, cp_len=c.cp_len,
+                         n_used=c.n_used, n_sym=c.n_sym, bits_per_sym=c.bits_per_sym,
+                         combiner=combiner, n_threads=n_threads)

@@ -1,0 +1,10 @@
+"""Seeded synthetic input generator shared by the oracle tests, the GPU tests and the benchmark.
+
+Holds the transmit side and the channel only (see ``rxgen.frames``); none of
+the receiver's arithmetic lives here.
+"""
+from .frames import (C1, C2, C2_20DB, C4, CONFIGS, FrameConfig, Frames, make_frames,
+                     qam_symbols, tap_delays_powers, used_subcarrier_bins)
+
+__all__ = ["C1", "C2", "C2_20DB", "C4", "CONFIGS", "FrameConfig", "Frames", "make_frames",
+           "qam_symbols", "tap_delays_powers", "used_subcarrier_bins"]

@@ -1,0 +1,238 @@
+#!/usr/bin/env python3
+"""Throughput of the uplink receive path (CP removal + FFT + LS + MRC + demap) on one MI355X.
+
+One step = ``rx_process_frame`` over every slot of the workload (the estimate
+and demod kernels), with the int16 input already resident in HBM.  Prints one
+JSON line.  Defaults: the 64-antenna, N=1024, 200-slot workload, 1 GPU.
+
+    python bench.py [--steps K] [--warmup W] [--workload c2|c1|c4] [--no-cpu]
+
+Besides the headline it reports, for the dominant kernel (demod), algorithmic
+bytes per launch / its average HIP-event-timed duration against the 8 TB/s
+HBM peak; the FP64 oracle timed on the host cores on the same workload; and
+LS NMSE, BER and EVM at 20 dB SNR.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1901_07499_amd", "csrc", f) for f in ("rx_kernels.hip", "rx_fft.hpp")]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_demod_c2.json")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(cfg, S: int, part: str) -> int:
+    """Bytes the method must move: payload samples (no CP) of the symbols a
+    call reads, the outputs it writes, and the channel estimate when it is an
+    input or output of the call.  Excludes CP samples and any re-reads."""
+    A, N, U, T, b = cfg.n_ant, cfg.fft_len, cfg.n_used, cfg.n_sym, cfg.bits_per_sym
+    Td = T - 1
+    out = Td * U * 8 + Td * U * b // 8       # x-hat (complex64) + packed bits
+    if part == "path":                        # whole path, H kept internal
+        return S * (T * A * N * 4 + out)
+    if part == "demod":                       # data symbols + H in, outputs
+        return S * (Td * A * N * 4 + A * U * 8 + out)
+    if part == "estimate":                    # pilot symbol in, H out
+        return S * (A * N * 4 + A * U * 8)
+    raise ValueError(part)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-quality", action="store_true", help="skip the 20 dB quality figures")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this receive path shards by slot with no exchange, "
+              "so multi-GPU throughput is N x the one-GPU figure; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    from rxgen import C1, C2, C2_20DB, C4, make_frames
+    cfg = {"c1": C1, "c2": C2, "c4": C4}[args.workload]
+    S = cfg.n_slots
+    workers = min(16, os.cpu_count() or 1)
+
+    # Generate every input before the process touches the GPU (fork-based pool).
+    t0 = time.time()
+    fr = make_frames(cfg, workers=workers)
+    log(f"generated {cfg.name}: {fr.iq.nbytes / 1e6:.1f} MB int16 in {time.time() - t0:.1f} s")
+    q20 = None
+    if not args.no_quality:
+        q_slots = min(S, 24)
+        q20 = make_frames(C2_20DB.replace(fft_len=cfg.fft_len, cp_len=cfg.cp_len, n_used=cfg.n_used,
+                                          n_ant=cfg.n_ant, bits_per_sym=cfg.bits_per_sym, n_sym=cfg.n_sym,
+                                          fs_hz=cfg.fs_hz),
+                          n_slots=q_slots, workers=workers)
+        log(f"generated {q_slots} slots at 20 dB for quality figures")
+
+    import numpy as np
+    import torch
+    from paper_1901_07499_amd import rx
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    plan = rx.Plan.from_config(cfg, fr.pilot)
+
+    # Host->device copy of the whole input, from pinned memory (context only).
+    pinned = torch.empty(fr.iq.shape, dtype=torch.int16, pin_memory=True)
+    pinned.numpy()[...] = fr.iq
+    iq = torch.empty(fr.iq.shape, dtype=torch.int16, device=dev)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    iq.copy_(pinned, non_blocking=True)
+    e1.record()
+    torch.cuda.synchronize()
+    h2d_ms = e0.elapsed_time(e1)
+    log(f"H2D {fr.iq.nbytes / 1e6:.1f} MB in {h2d_ms:.2f} ms")
+
+    Td = cfg.n_sym - 1
+    xhat = torch.empty((S, Td, cfg.n_used, 2), dtype=torch.float32, device=dev)
+    bits = torch.empty((S, Td, plan.row_bytes), dtype=torch.uint8, device=dev)
+    ws = torch.empty(plan.workspace_bytes(S), dtype=torch.uint8, device=dev)
+    out = (None, xhat, bits)
+
+    for _ in range(args.warmup):
+        plan.process(iq, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    log(f"warmup {args.warmup} done")
+
+    t_start, t_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record()
+    for _ in range(args.steps):
+        plan.process(iq, out=out, workspace=ws)
+    t_end.record()
+    torch.cuda.synchronize()
+    ms_per_step = t_start.elapsed_time(t_end) / args.steps
+    samples_per_step = S * cfg.n_sym * cfg.n_ant * (cfg.fft_len + cfg.cp_len)
+    value = samples_per_step / (ms_per_step * 1e-3)
+    log(f"timed {args.steps} steps: {ms_per_step:.4f} ms/step, {value:.4e} antenna-samples/s")
+
+    # Per-kernel durations over the same work: events around each launch on the launch stream.
+    H = torch.empty((S, cfg.n_ant, cfg.n_used, 2), dtype=torch.float32, device=dev)
+    reps = max(args.steps, 10)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(reps)]
+    for r in range(reps):
+        ev[r][0].record()
+        plan.estimate(iq, H=H)
+        ev[r][1].record()
+        st = rx.rx_demod(plan._plan, iq.data_ptr(), H.data_ptr(), S, xhat.data_ptr(), bits.data_ptr(), None,
+                         torch.cuda.current_stream().cuda_stream)
+        assert st == rx.RX_OK
+        ev[r][2].record()
+    torch.cuda.synchronize()
+    est_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / reps
+    dem_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / reps
+    dem_bytes = algorithmic_bytes(cfg, S, "demod")
+    achieved = dem_bytes / (dem_ms * 1e-3) / 1e9
+    log(f"estimate {est_ms:.4f} ms, demod {dem_ms:.4f} ms -> demod {achieved:.1f} GB/s algorithmic")
+
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        t = json.load(open(TRAFFIC_FILE))
+        if t.get("kernel_hash") == kernel_hash() and t.get("workload") == cfg.name:
+            traffic = t.get("bytes_per_launch")
+    roofline = {"bound": "hbm", "kernel": "demod_kernel", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "algorithmic_bytes_per_launch": dem_bytes,
+                "avg_launch_ms": round(dem_ms, 5)}
+    path_bytes = algorithmic_bytes(cfg, S, "path")
+    path_gbs = path_bytes / (ms_per_step * 1e-3) / 1e9
+
+    quality = None
+    if q20 is not None:
+        import oracle as _o  # noqa: F401  (quality figures compare with the transmitted truth only)
+        qplan = rx.Plan.from_config(q20.cfg, q20.pilot)
+        qH, qx, qb = qplan.process(torch.from_numpy(q20.iq).to(dev), want_H=True)
+        torch.cuda.synchronize()
+        Hg = qH.cpu().numpy().astype(np.float64)
+        Hg = Hg[..., 0] + 1j * Hg[..., 1]
+        N = q20.cfg.fft_len
+        nmse = np.mean(np.abs(Hg - q20.H_true) ** 2 / (N * q20.scale[:, None, None] ** 2))
+        xg = qx.cpu().numpy().astype(np.float64)
+        xg = xg[..., 0] + 1j * xg[..., 1]
+        evm = float(np.sqrt(np.mean(np.abs(xg - q20.X) ** 2)))
+        nerr = int(np.unpackbits(qb.cpu().numpy() ^ q20.packed_bits()).sum())
+        nbits = int(q20.bits.size)
+        quality = {"snr_db": 20.0, "slots": int(q20.iq.shape[0]), "ls_nmse_db": round(10 * np.log10(nmse), 3),
+                   "evm_rms": round(evm, 5), "bit_errors": nerr, "bits": nbits,
+                   "ber": nerr / nbits, "ber_95_upper": (3.0 / nbits if nerr == 0 else None)}
+        log(f"quality at 20 dB: {quality}")
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        threads = min(16, os.cpu_count() or 1)
+        n_cpu = S
+        t0 = time.perf_counter()
+        oracle.run_config(fr, n_threads=threads, slots=slice(0, n_cpu))
+        dt = time.perf_counter() - t0
+        if dt < 10.0 and n_cpu == S:   # repeat the pass to reach a stable ~10 s sample
+            reps_cpu = max(1, int(10.0 / max(dt, 1e-3)))
+            t0 = time.perf_counter()
+            for _ in range(reps_cpu):
+                oracle.run_config(fr, n_threads=threads)
+            dt = (time.perf_counter() - t0) / reps_cpu
+        cpu_value = n_cpu * cfg.n_sym * cfg.n_ant * (cfg.fft_len + cfg.cp_len) / dt
+        cpu = {"value": cpu_value, "unit": "antenna-samples/s", "cores": threads, "kind": "oracle",
+               "sample": f"all {n_cpu} slots of {cfg.name}, FP64 C oracle, {threads} threads, "
+                         f"{dt:.3f} s per pass"}
+        log(f"cpu baseline {cpu_value:.4e} antenna-samples/s on {threads} threads")
+
+    rec = {
+        "metric": "antenna-samples/s through FFT+LS+demod, % HBM peak; BER/NMSE at 20 dB vs plain",
+        "value": value,
+        "unit": "antenna-samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": cfg.name, "n_ant": cfg.n_ant, "fft_len": cfg.fft_len, "cp_len": cfg.cp_len,
+                   "n_sym": cfg.n_sym, "n_used": cfg.n_used, "bits_per_sym": cfg.bits_per_sym,
+                   "n_slots": S, "combiner": "mrc", "input": "int16 IQ resident in HBM"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "path_algorithmic_GBps": round(path_gbs, 1),
+        "path_hbm_frac": round(path_gbs / HBM_PEAK_GBS, 4),
+        "estimate_ms": round(est_ms, 5),
+        "demod_ms": round(dem_ms, 5),
+        "h2d_ms_pinned": round(h2d_ms, 3),
+        "h2d_inclusive_antenna_samples_per_s": samples_per_step / ((ms_per_step + h2d_ms) * 1e-3),
+        "quality_20db": quality,
+        "kernel_hash": kernel_hash(),
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

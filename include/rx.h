@@ -1,0 +1,138 @@
+/*
+ * rx.h -- C ABI of the MI355X (gfx950) uplink OFDM receive library librx.so.
+ *
+ * The library runs the receive path of a single-user, many-antenna uplink:
+ * int16 IQ samples of every antenna and OFDM symbol -> cyclic-prefix removal
+ * -> N-point FFT per antenna and symbol -> block least-squares channel
+ * estimate from the first (pilot) symbol -> combining over the antennas
+ * (maximal ratio, or zero forcing for one user) -> hard QAM decisions packed
+ * into bytes.
+ *
+ * The operations follow the paper (Gokalgandhi et al., "Accelerating Channel
+ * Estimation and Demodulation of Uplink OFDM symbols for Large Scale Antenna
+ * Systems using GPU"): the CP is dropped and an FFT taken for every antenna's
+ * symbol (Sec. II-B, II-C); the first symbol gives the LS estimate, the
+ * received subcarrier divided by the pilot (Sec. II-B; Sec. II-C, LS
+ * paragraph); later symbols are combined per subcarrier over all antennas by
+ * MRC (Sec. II-C, MRC paragraph); subcarriers are in fftshift order
+ * (Sec. II-C, last sentence).  Where the paper is silent this library fixes:
+ *   - FFT: Y[k] = sum_n y[n] exp(-2 pi i k n / N), no scaling;
+ *   - used subcarrier d (0..U-1) has signed frequency d-U/2 for d < U/2 and
+ *     d-U/2+1 otherwise, i.e. FFT bin k_d = f_d mod N (DC, Nyquist unused);
+ *   - LS: H[a][d] = Y_0[a][k_d] * conj(X_p[d]) / |X_p[d]|^2;
+ *   - MRC: xhat = sum_a conj(H[a][d]) Y_t[a][k_d] / g[d], g[d] = sum_a |H[a][d]|^2,
+ *     and xhat = 0 when g[d] == 0;  ZF (one user): xhat = sum_a w_a Y_t[a][k_d],
+ *     w_a = conj(H[a][d]) / g[d];
+ *   - decisions per axis with strict comparisons (a value exactly on a
+ *     threshold, or -0.0, gives bit 0): first bit of an axis = [c < 0];
+ *     16-QAM second bit = [|c| sqrt(10) > 2]; 64-QAM second = [|c| sqrt(42) > 4],
+ *     third = [| |c| sqrt(42) - 4 | > 2]; bits of the real axis take even
+ *     positions b0, b2, b4 and of the imaginary axis odd positions b1, b3, b5;
+ *   - bits are packed MSB-first in the order [slot][data symbol][d][b0..].
+ *
+ * Memory layouts (all row-major, C order; "complex" = two floats re, im):
+ *   iq    int16   [S][T][A][CP+N][2]     input, 4-byte aligned
+ *   H     float   [S][A][U][2]           LS channel estimate, 8-byte aligned
+ *   g     float   [S][U]                 sum over antennas of |H|^2
+ *   xhat  float   [S][T-1][U][2]         combined data symbols, 8-byte aligned
+ *   bits  uint8   [S][T-1][U*b/8]        hard decisions, packed
+ * S = n_slots, T = n_sym (symbol 0 is the pilot), A = n_ant, N = fft_len,
+ * CP = cp_len, U = n_used, b = bits_per_sym.
+ *
+ * Ownership: every data pointer passed to the compute calls is a DEVICE
+ * pointer owned by the caller and valid on the plan's device.  The plan owns
+ * a copy of the parameters and small device tables (twiddles, pilot factors;
+ * a few tens of KB) created in rx_plan_create and freed in rx_plan_destroy.
+ * Scratch beyond that is caller-provided (see rx_workspace_bytes).
+ *
+ * Errors: every argument check runs before anything is launched, so a call
+ * that returns an error has written nothing.  Compute calls are asynchronous
+ * on the given HIP stream (NULL = the null stream); faults during execution
+ * surface at the caller's next synchronisation.  A plan is immutable after
+ * creation and may be used from several streams at once provided each call
+ * has its own output and workspace buffers.
+ */
+#ifndef RX_H
+#define RX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rx_plan_s* rx_plan_t;
+
+enum rx_status {
+  RX_OK = 0,
+  RX_E_INVALID_ARG = -1, /* bad shape, null/misaligned pointer, zero pilot, wrong device */
+  RX_E_UNSUPPORTED = -2, /* valid but not implemented: N not a power of two in 64..2048,
+                            bits_per_sym not in {2,4,6}, more than one user, unknown combiner */
+  RX_E_HIP = -3,         /* a HIP runtime call or kernel launch failed */
+  RX_E_NOMEM = -4        /* device or host allocation failed */
+};
+
+enum rx_combiner { RX_COMB_MRC = 0, RX_COMB_ZF = 1 };
+
+typedef struct {
+  int32_t n_ant;        /* A >= 1 receive antennas */
+  int32_t fft_len;      /* N, a power of two in [64, 2048] */
+  int32_t cp_len;       /* CP, 0 <= CP < N */
+  int32_t n_used;       /* U, even, 2 <= U <= N-2, and U*b a multiple of 8 */
+  int32_t n_sym;        /* T >= 2: symbol 0 = pilot, 1..T-1 = data */
+  int32_t bits_per_sym; /* b: 2 (QPSK), 4 (16-QAM), 6 (64-QAM) */
+  int32_t combiner;     /* RX_COMB_MRC or RX_COMB_ZF */
+  int32_t n_users;      /* K, must be 1 (single-user uplink) */
+  const float* pilot;   /* HOST pointer to U complex pilot values in d order;
+                           every value non-zero and finite; copied by rx_plan_create */
+} rx_params;
+
+/* Validate parameters without touching the GPU.  Returns RX_OK or the status
+ * rx_plan_create would return for them. */
+int rx_params_check(const rx_params* p);
+
+/* Create a plan on the current HIP device.  *out is set only on RX_OK. */
+int rx_plan_create(const rx_params* p, rx_plan_t* out);
+
+/* Release a plan and its device tables.  NULL is accepted (no-op). */
+int rx_plan_destroy(rx_plan_t plan);
+
+/* Bytes of device scratch that rx_process_frame needs when H == NULL
+ * (it then keeps the channel estimate there): S*A*U*8.  0 for a NULL plan or
+ * n_slots <= 0.  rx_estimate and rx_demod need none. */
+size_t rx_workspace_bytes(rx_plan_t plan, int64_t n_slots);
+
+/* Channel estimation (paper Sec. II-B, first symbol; Sec. II-C, LS):
+ * CP removal + FFT of the pilot symbol of every antenna, then
+ * H[s][a][d] = Y_0[s][a][k_d] * conj(X_p[d]) / |X_p[d]|^2.
+ * iq required; H required; g optional (NULL = not computed); workspace unused. */
+int rx_estimate(rx_plan_t plan, const int16_t* iq, int64_t n_slots, float* H, float* g,
+                void* workspace, void* hip_stream);
+
+/* Demodulation of the data symbols (paper Sec. II-B; Sec. II-C, MRC): CP
+ * removal + FFT of symbols 1..T-1 of every antenna, combining with the given
+ * channel estimate H (layout above, e.g. from rx_estimate), hard decisions.
+ * xhat and bits are optional but not both NULL; workspace unused. */
+int rx_demod(rx_plan_t plan, const int16_t* iq, const float* H, int64_t n_slots, float* xhat,
+             uint8_t* bits, void* workspace, void* hip_stream);
+
+/* The whole path for S slots: rx_estimate followed by rx_demod on one stream.
+ * H optional: when NULL the estimate is kept in `workspace`
+ * (>= rx_workspace_bytes(plan, n_slots) bytes, 256-byte aligned).
+ * xhat and bits optional but not both NULL. */
+int rx_process_frame(rx_plan_t plan, const int16_t* iq, int64_t n_slots, float* H, float* xhat,
+                     uint8_t* bits, void* workspace, void* hip_stream);
+
+/* CP removal + FFT only, for every symbol of every antenna:
+ * Y float [S][T][A][N][2] in natural bin order.  For validating the FFT stage. */
+int rx_debug_fft(rx_plan_t plan, const int16_t* iq, int64_t n_slots, float* Y, void* hip_stream);
+
+/* Static description of a status code. */
+const char* rx_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RX_H */

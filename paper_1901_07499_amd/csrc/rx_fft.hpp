@@ -1,0 +1,256 @@
+// rx_fft.hpp -- wavefront-level FFT building blocks for gfx950.
+//
+// An N-point FFT (N = 64 .. 2048) is computed by L = N / P lanes of one
+// 64-wide wavefront, each lane holding P complex points in VGPRs (P = 16, or
+// 32 for N = 2048); for N < 1024 one wavefront runs F = 64 / L transforms side
+// by side.  The transform is a self-sorting (Stockham) sequence of radix-R
+// passes: each lane applies R-point DFTs to R of its points held in registers,
+// and consecutive passes exchange data through a private, padded LDS region of
+// the wavefront.  No workgroup barrier is involved: a wavefront's LDS
+// operations execute in program order, so a wavefront-scope fence (a pure
+// compiler ordering point) separates the reads and writes of each pass.
+//
+// Pass with radix R after stride NS (product of the earlier radices):
+// butterfly j in [0, N/R) takes x[j + r*N/R], r = 0..R-1, multiplies element r
+// by W^(r*(j mod NS)) with W = exp(-2 pi i / (NS*R)), takes the R-point DFT and
+// stores output r at (j / NS)*NS*R + (j mod NS) + r*NS.  After the last pass
+// the spectrum is in natural order.
+//
+// The transform computed is Y[k] = sum_n y[n] exp(-2 pi i k n / N) (forward,
+// unscaled) -- the FFT taken after CP removal on every antenna (paper
+// Sec. II-B, Sec. II-C).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rx {
+
+// ------------------------------------------------------------ complex helpers
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+// a * w
+__device__ __forceinline__ float2 cmul(float2 a, float2 w) {
+  return make_float2(fmaf(a.x, w.x, -a.y * w.y), fmaf(a.x, w.y, a.y * w.x));
+}
+// a * (-i)
+__device__ __forceinline__ float2 mul_mi(float2 a) { return make_float2(a.y, -a.x); }
+// a * exp(-i pi/4) = a * (1 - i)/sqrt(2)
+__device__ __forceinline__ float2 mul_w8_1(float2 a) {
+  const float c = 0.70710678118654752f;
+  return make_float2((a.x + a.y) * c, (a.y - a.x) * c);
+}
+// a * exp(-3 i pi/4) = a * (-1 - i)/sqrt(2)
+__device__ __forceinline__ float2 mul_w8_3(float2 a) {
+  const float c = 0.70710678118654752f;
+  return make_float2((a.y - a.x) * c, -(a.x + a.y) * c);
+}
+
+// ------------------------------------------------------------ R-point DFTs in registers
+// All take v[o .. o+R) in natural order and leave the DFT there in natural
+// order.  `o` is a compile-time constant after unrolling.
+template <int P>
+__device__ __forceinline__ void dft2(float2 (&v)[P], int o) {
+  float2 a = v[o], b = v[o + 1];
+  v[o] = cadd(a, b);
+  v[o + 1] = csub(a, b);
+}
+
+// 4-point DFT of (a0, a1, a2, a3) in place.
+__device__ __forceinline__ void dft4_raw(float2& a0, float2& a1, float2& a2, float2& a3) {
+  float2 t0 = cadd(a0, a2), t1 = csub(a0, a2);
+  float2 t2 = cadd(a1, a3), t3 = mul_mi(csub(a1, a3));
+  a0 = cadd(t0, t2);
+  a2 = csub(t0, t2);
+  a1 = cadd(t1, t3);
+  a3 = csub(t1, t3);
+}
+
+template <int P>
+__device__ __forceinline__ void dft4(float2 (&v)[P], int o) {
+  dft4_raw(v[o], v[o + 1], v[o + 2], v[o + 3]);
+}
+
+// 8 = 2 x 4: even/odd 4-point DFTs, then one radix-2 layer with W8^k.
+template <int P>
+__device__ __forceinline__ void dft8(float2 (&v)[P], int o) {
+  float2 e0 = v[o], e1 = v[o + 2], e2 = v[o + 4], e3 = v[o + 6];
+  float2 d0 = v[o + 1], d1 = v[o + 3], d2 = v[o + 5], d3 = v[o + 7];
+  dft4_raw(e0, e1, e2, e3);
+  dft4_raw(d0, d1, d2, d3);
+  d1 = mul_w8_1(d1);
+  d2 = mul_mi(d2);
+  d3 = mul_w8_3(d3);
+  v[o + 0] = cadd(e0, d0);
+  v[o + 4] = csub(e0, d0);
+  v[o + 1] = cadd(e1, d1);
+  v[o + 5] = csub(e1, d1);
+  v[o + 2] = cadd(e2, d2);
+  v[o + 6] = csub(e2, d2);
+  v[o + 3] = cadd(e3, d3);
+  v[o + 7] = csub(e3, d3);
+}
+
+// 16 = 4 x 4: n = n1 + 4 n2, k = k2 + 4 k1;
+// X[k2 + 4 k1] = sum_n1 W4^(n1 k1) W16^(n1 k2) sum_n2 x[n1 + 4 n2] W4^(n2 k2).
+template <int P>
+__device__ __forceinline__ void dft16(float2 (&v)[P], int o) {
+  const float2 w1 = make_float2(0.92387953251128674f, -0.38268343236508977f);  // W16^1
+  const float2 w3 = make_float2(0.38268343236508977f, -0.92387953251128674f);  // W16^3
+  // inner 4-point DFTs over n2 for each n1; results a[n1][k2] stay at v[o + n1 + 4 k2]
+#pragma unroll
+  for (int n1 = 0; n1 < 4; n1++) dft4_raw(v[o + n1], v[o + n1 + 4], v[o + n1 + 8], v[o + n1 + 12]);
+  // twiddles W16^(n1 k2)
+  v[o + 1 + 4] = cmul(v[o + 1 + 4], w1);          // n1=1,k2=1
+  v[o + 1 + 8] = mul_w8_1(v[o + 1 + 8]);          // n1=1,k2=2 : W16^2
+  v[o + 1 + 12] = cmul(v[o + 1 + 12], w3);        // n1=1,k2=3
+  v[o + 2 + 4] = mul_w8_1(v[o + 2 + 4]);          // n1=2,k2=1 : W16^2
+  v[o + 2 + 8] = mul_mi(v[o + 2 + 8]);            // n1=2,k2=2 : W16^4
+  v[o + 2 + 12] = mul_w8_3(v[o + 2 + 12]);        // n1=2,k2=3 : W16^6
+  v[o + 3 + 4] = cmul(v[o + 3 + 4], w3);          // n1=3,k2=1
+  v[o + 3 + 8] = mul_w8_3(v[o + 3 + 8]);          // n1=3,k2=2 : W16^6
+  {                                               // n1=3,k2=3 : W16^9 = -W16^1
+    float2 t = cmul(v[o + 3 + 12], w1);
+    v[o + 3 + 12] = make_float2(-t.x, -t.y);
+  }
+  // outer 4-point DFTs over n1 for each k2; output k = k2 + 4 k1
+  float2 r[16];
+#pragma unroll
+  for (int k2 = 0; k2 < 4; k2++) {
+    float2 a0 = v[o + 4 * k2], a1 = v[o + 1 + 4 * k2], a2 = v[o + 2 + 4 * k2], a3 = v[o + 3 + 4 * k2];
+    dft4_raw(a0, a1, a2, a3);
+    r[k2] = a0;
+    r[k2 + 4] = a1;
+    r[k2 + 8] = a2;
+    r[k2 + 12] = a3;
+  }
+#pragma unroll
+  for (int k = 0; k < 16; k++) v[o + k] = r[k];
+}
+
+template <int R, int P>
+__device__ __forceinline__ void dft(float2 (&v)[P], int o) {
+  if constexpr (R == 2) dft2(v, o);
+  else if constexpr (R == 4) dft4(v, o);
+  else if constexpr (R == 8) dft8(v, o);
+  else if constexpr (R == 16) dft16(v, o);
+  else static_assert(R == 2 || R == 4 || R == 8 || R == 16, "unsupported radix");
+}
+
+// ------------------------------------------------------------ LDS layout
+// One complex of padding every 16 keeps the 16-point stride of the first
+// pass's writes off a single bank.
+__device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
+template <int N>
+struct Lds {
+  static constexpr int kSlot = N + N / 16;  // float2 per transform
+};
+
+__device__ __forceinline__ void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ------------------------------------------------------------ pass schedule per N
+template <int N>
+struct FftShape {
+  static constexpr int P = (N >= 2048) ? 32 : 16;  // points per lane
+  static constexpr int L = N / P;                  // lanes per transform
+  static constexpr int F = 64 / L;                 // transforms per wavefront
+  static_assert(N >= 64 && N <= 2048 && (N & (N - 1)) == 0, "N must be a power of two in [64, 2048]");
+};
+
+// One Stockham pass.  On entry (FIRST) v holds this lane's inputs
+// v[m*R + r] = x[j_m + r*N/R], j_m = li + L*m; otherwise they are gathered
+// from `buf`.  Output goes to `buf` (padded indexing).
+template <int N, int R, int NS, bool FIRST>
+__device__ __forceinline__ void stockham_pass(float2 (&v)[FftShape<N>::P], float2* buf, int li,
+                                              const float2* __restrict__ tw) {
+  constexpr int P = FftShape<N>::P;
+  constexpr int L = FftShape<N>::L;
+  constexpr int NB = P / R;
+  static_assert(P % R == 0, "radix must divide the points per lane");
+  if constexpr (!FIRST) {
+#pragma unroll
+    for (int m = 0; m < NB; m++) {
+      const int j = li + L * m;
+#pragma unroll
+      for (int r = 0; r < R; r++) v[m * R + r] = buf[pad(j + r * (N / R))];
+    }
+    wave_fence();  // every lane's reads happen before any lane's writes
+  }
+#pragma unroll
+  for (int m = 0; m < NB; m++) {
+    const int j = li + L * m;
+    if constexpr (NS > 1) {
+      const int jm = j & (NS - 1);
+      const int step = jm * (N / (NS * R));
+#pragma unroll
+      for (int r = 1; r < R; r++) v[m * R + r] = cmul(v[m * R + r], tw[step * r]);
+    }
+    dft<R>(v, m * R);
+    const int o = (j / NS) * NS * R + (j & (NS - 1));
+#pragma unroll
+    for (int r = 0; r < R; r++) buf[pad(o + r * NS)] = v[m * R + r];
+  }
+  wave_fence();
+}
+
+// Whole transform: inputs in v (first-pass order), spectrum left in `buf` in
+// natural order (padded indexing).  `tw[k]` = exp(-2 pi i k / N), k < N.
+template <int N>
+__device__ __forceinline__ void fft_to_lds(float2 (&v)[FftShape<N>::P], float2* buf, int li,
+                                           const float2* __restrict__ tw) {
+  if constexpr (N == 64) {
+    stockham_pass<N, 16, 1, true>(v, buf, li, tw);
+    stockham_pass<N, 4, 16, false>(v, buf, li, tw);
+  } else if constexpr (N == 128) {
+    stockham_pass<N, 16, 1, true>(v, buf, li, tw);
+    stockham_pass<N, 8, 16, false>(v, buf, li, tw);
+  } else if constexpr (N == 256) {
+    stockham_pass<N, 16, 1, true>(v, buf, li, tw);
+    stockham_pass<N, 16, 16, false>(v, buf, li, tw);
+  } else if constexpr (N == 512) {
+    stockham_pass<N, 16, 1, true>(v, buf, li, tw);
+    stockham_pass<N, 8, 16, false>(v, buf, li, tw);
+    stockham_pass<N, 4, 128, false>(v, buf, li, tw);
+  } else if constexpr (N == 1024) {
+    stockham_pass<N, 16, 1, true>(v, buf, li, tw);
+    stockham_pass<N, 16, 16, false>(v, buf, li, tw);
+    stockham_pass<N, 4, 256, false>(v, buf, li, tw);
+  } else if constexpr (N == 2048) {
+    stockham_pass<N, 16, 1, true>(v, buf, li, tw);
+    stockham_pass<N, 16, 16, false>(v, buf, li, tw);
+    stockham_pass<N, 8, 256, false>(v, buf, li, tw);
+  }
+}
+
+// int16 I/Q packed in one dword (I in the low half) -> complex float, exact.
+__device__ __forceinline__ float2 iq_to_float(uint32_t w) {
+  return make_float2((float)(int16_t)(w & 0xffffu), (float)((int32_t)w >> 16));
+}
+
+// Load this lane's first-pass inputs for one symbol: x[n] = sample CP + n of
+// the record starting at `rec` (dword per complex sample).
+template <int N>
+__device__ __forceinline__ void load_symbol(uint32_t (&raw)[FftShape<N>::P], const uint32_t* __restrict__ rec,
+                                            int li, bool valid) {
+  constexpr int P = FftShape<N>::P;
+  constexpr int L = FftShape<N>::L;
+  constexpr int R = 16;  // first pass radix for every N
+  constexpr int NB = P / R;
+#pragma unroll
+  for (int m = 0; m < NB; m++)
+#pragma unroll
+    for (int r = 0; r < R; r++)
+      raw[m * R + r] = valid ? __builtin_nontemporal_load(rec + li + L * m + r * (N / R)) : 0u;
+}
+
+template <int N>
+__device__ __forceinline__ void unpack_symbol(float2 (&v)[FftShape<N>::P], const uint32_t (&raw)[FftShape<N>::P]) {
+#pragma unroll
+  for (int i = 0; i < FftShape<N>::P; i++) v[i] = iq_to_float(raw[i]);
+}
+
+}  // namespace rx

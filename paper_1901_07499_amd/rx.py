@@ -1,0 +1,226 @@
+"""Thin Python binding of ``librx.so`` (the C ABI in ``include/rx.h``).
+
+Argument marshalling only: every step of the receive path runs in the HIP
+kernels behind the C calls.  PyTorch provides device memory and the stream.
+The module-level functions carry the C names and take raw integer pointers;
+``Plan`` wraps them for torch tensors.  If ``librx.so`` has not been built the
+import fails with an explicit error -- there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librx.so")
+
+RX_OK, RX_E_INVALID_ARG, RX_E_UNSUPPORTED, RX_E_HIP, RX_E_NOMEM = 0, -1, -2, -3, -4
+RX_COMB_MRC, RX_COMB_ZF = 0, 1
+
+# Every symbol the header declares; the CPU test checks they are all exported.
+EXPORTS = ("rx_params_check", "rx_plan_create", "rx_plan_destroy", "rx_workspace_bytes", "rx_estimate",
+           "rx_demod", "rx_process_frame", "rx_debug_fft", "rx_status_string")
+
+
+class RxError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {rx_status_string(status)} ({status})")
+        self.status = status
+
+
+class rx_params(ctypes.Structure):
+    _fields_ = [("n_ant", ctypes.c_int32), ("fft_len", ctypes.c_int32), ("cp_len", ctypes.c_int32),
+                ("n_used", ctypes.c_int32), ("n_sym", ctypes.c_int32), ("bits_per_sym", ctypes.c_int32),
+                ("combiner", ctypes.c_int32), ("n_users", ctypes.c_int32),
+                ("pilot", ctypes.POINTER(ctypes.c_float))]
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1901_07499_amd.build` "
+                          "(the receive path has no non-HIP implementation)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t
+    lib.rx_params_check.argtypes = [ctypes.POINTER(rx_params)]
+    lib.rx_plan_create.argtypes = [ctypes.POINTER(rx_params), ctypes.POINTER(vp)]
+    lib.rx_plan_destroy.argtypes = [vp]
+    lib.rx_workspace_bytes.argtypes = [vp, i64]
+    lib.rx_workspace_bytes.restype = sz
+    lib.rx_estimate.argtypes = [vp, vp, i64, vp, vp, vp, vp]
+    lib.rx_demod.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp]
+    lib.rx_process_frame.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp]
+    lib.rx_debug_fft.argtypes = [vp, vp, i64, vp, vp]
+    lib.rx_status_string.argtypes = [ctypes.c_int]
+    lib.rx_status_string.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name not in ("rx_workspace_bytes", "rx_status_string"):
+            getattr(lib, name).restype = ctypes.c_int
+    return lib
+
+
+_lib = _load()
+
+
+# ---------------------------------------------------------------- C names, raw pointers
+def rx_params_check(p: rx_params) -> int:
+    return _lib.rx_params_check(ctypes.byref(p))
+
+
+def rx_plan_create(p: rx_params) -> Tuple[int, Optional[int]]:
+    out = ctypes.c_void_p()
+    st = _lib.rx_plan_create(ctypes.byref(p), ctypes.byref(out))
+    return st, (out.value if st == RX_OK else None)
+
+
+def rx_plan_destroy(plan: Optional[int]) -> int:
+    return _lib.rx_plan_destroy(plan)
+
+
+def rx_workspace_bytes(plan: Optional[int], n_slots: int) -> int:
+    return _lib.rx_workspace_bytes(plan, n_slots)
+
+
+def rx_estimate(plan, iq, n_slots, H, g, workspace, stream) -> int:
+    return _lib.rx_estimate(plan, iq, n_slots, H, g, workspace, stream)
+
+
+def rx_demod(plan, iq, H, n_slots, xhat, bits, workspace, stream) -> int:
+    return _lib.rx_demod(plan, iq, H, n_slots, xhat, bits, workspace, stream)
+
+
+def rx_process_frame(plan, iq, n_slots, H, xhat, bits, workspace, stream) -> int:
+    return _lib.rx_process_frame(plan, iq, n_slots, H, xhat, bits, workspace, stream)
+
+
+def rx_debug_fft(plan, iq, n_slots, Y, stream) -> int:
+    return _lib.rx_debug_fft(plan, iq, n_slots, Y, stream)
+
+
+def rx_status_string(status: int) -> str:
+    return _lib.rx_status_string(status).decode()
+
+
+def make_params(n_ant: int, fft_len: int, cp_len: int, n_used: int, n_sym: int, bits_per_sym: int,
+                pilot: Sequence[complex], combiner: int = RX_COMB_MRC, n_users: int = 1):
+    """Build an ``rx_params`` plus the float buffer its pilot pointer refers to (keep both alive)."""
+    pil = np.ascontiguousarray(np.asarray(pilot, dtype=np.complex64)).view(np.float32)
+    p = rx_params(n_ant, fft_len, cp_len, n_used, n_sym, bits_per_sym, combiner, n_users,
+                  pil.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+    return p, pil
+
+
+# ---------------------------------------------------------------- torch-level wrapper
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+class Plan:
+    """A receive plan on the current CUDA (HIP) device.
+
+    ``iq`` tensors are int16 [S][T][A][CP+N][2] on that device.  Outputs are
+    float32 tensors with a trailing (re, im) axis and uint8 packed bits, laid
+    out as in ``include/rx.h``.  Calls are queued on torch's current stream.
+    """
+
+    def __init__(self, n_ant: int, fft_len: int, cp_len: int, n_used: int, n_sym: int, bits_per_sym: int,
+                 pilot: Sequence[complex], combiner: int = RX_COMB_MRC, n_users: int = 1):
+        self.n_ant, self.fft_len, self.cp_len, self.n_used = n_ant, fft_len, cp_len, n_used
+        self.n_sym, self.bits_per_sym, self.combiner = n_sym, bits_per_sym, combiner
+        self._params, self._pilot = make_params(n_ant, fft_len, cp_len, n_used, n_sym, bits_per_sym, pilot,
+                                                combiner, n_users)
+        st, self._plan = rx_plan_create(self._params)
+        if st != RX_OK:
+            raise RxError(st, "rx_plan_create")
+
+    @classmethod
+    def from_config(cls, cfg, pilot, combiner: int = RX_COMB_MRC) -> "Plan":
+        return cls(cfg.n_ant, cfg.fft_len, cfg.cp_len, cfg.n_used, cfg.n_sym, cfg.bits_per_sym, pilot, combiner)
+
+    def close(self):
+        if getattr(self, "_plan", None):
+            rx_plan_destroy(self._plan)
+            self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # shapes
+    def _slots(self, iq) -> int:
+        import torch
+        want = (self.n_sym, self.n_ant, self.fft_len + self.cp_len, 2)
+        if iq.dtype != torch.int16 or tuple(iq.shape[1:]) != want or not iq.is_contiguous() or not iq.is_cuda:
+            raise ValueError(f"iq must be a contiguous int16 CUDA tensor of shape [S, {', '.join(map(str, want))}]")
+        return iq.shape[0]
+
+    def _empty(self, shape, dtype, like):
+        import torch
+        return torch.empty(shape, dtype=dtype, device=like.device)
+
+    def _stream(self) -> int:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+
+    @property
+    def row_bytes(self) -> int:
+        return self.n_used * self.bits_per_sym // 8
+
+    def workspace_bytes(self, n_slots: int) -> int:
+        return rx_workspace_bytes(self._plan, n_slots)
+
+    def estimate(self, iq, H=None, with_g: bool = False):
+        import torch
+        S = self._slots(iq)
+        H = self._empty((S, self.n_ant, self.n_used, 2), torch.float32, iq) if H is None else H
+        g = self._empty((S, self.n_used), torch.float32, iq) if with_g else None
+        st = rx_estimate(self._plan, iq.data_ptr(), S, H.data_ptr(), _ptr(g), None, self._stream())
+        if st != RX_OK:
+            raise RxError(st, "rx_estimate")
+        return (H, g) if with_g else H
+
+    def demod(self, iq, H, want_xhat: bool = True, want_bits: bool = True):
+        import torch
+        S = self._slots(iq)
+        Td = self.n_sym - 1
+        xhat = self._empty((S, Td, self.n_used, 2), torch.float32, iq) if want_xhat else None
+        bits = self._empty((S, Td, self.row_bytes), torch.uint8, iq) if want_bits else None
+        st = rx_demod(self._plan, iq.data_ptr(), H.data_ptr(), S, _ptr(xhat), _ptr(bits), None, self._stream())
+        if st != RX_OK:
+            raise RxError(st, "rx_demod")
+        return xhat, bits
+
+    def process(self, iq, want_H: bool = False, want_xhat: bool = True, want_bits: bool = True, out=None,
+                workspace=None):
+        """Whole path.  ``out`` = (H or None, xhat or None, bits or None) preallocated buffers."""
+        import torch
+        S = self._slots(iq)
+        Td = self.n_sym - 1
+        if out is not None:
+            H, xhat, bits = out
+        else:
+            H = self._empty((S, self.n_ant, self.n_used, 2), torch.float32, iq) if want_H else None
+            xhat = self._empty((S, Td, self.n_used, 2), torch.float32, iq) if want_xhat else None
+            bits = self._empty((S, Td, self.row_bytes), torch.uint8, iq) if want_bits else None
+        ws = None
+        if H is None:
+            ws = workspace if workspace is not None else self._empty((max(1, self.workspace_bytes(S)),),
+                                                                     torch.uint8, iq)
+        st = rx_process_frame(self._plan, iq.data_ptr(), S, _ptr(H), _ptr(xhat), _ptr(bits), _ptr(ws),
+                              self._stream())
+        if st != RX_OK:
+            raise RxError(st, "rx_process_frame")
+        return H, xhat, bits
+
+    def debug_fft(self, iq):
+        import torch
+        S = self._slots(iq)
+        Y = self._empty((S, self.n_sym, self.n_ant, self.fft_len, 2), torch.float32, iq)
+        st = rx_debug_fft(self._plan, iq.data_ptr(), S, Y.data_ptr(), self._stream())
+        if st != RX_OK:
+            raise RxError(st, "rx_debug_fft")
+        return Y

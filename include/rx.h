@@ -46,7 +46,8 @@
  * Scratch beyond that is caller-provided (see rx_workspace_bytes).
  *
  * Errors: every argument check runs before anything is launched, so a call
- * that returns an error has written nothing.  Compute calls are asynchronous
+ * that returns an error has written nothing.  n_slots == 0 is a valid no-op
+ * (only the plan is checked; data pointers may then be NULL).  Compute calls are asynchronous
  * on the given HIP stream (NULL = the null stream); faults during execution
  * surface at the caller's next synchronisation.  A plan is immutable after
  * creation and may be used from several streams at once provided each call

@@ -160,10 +160,9 @@ int rx_estimate(rx_plan_t plan, const int16_t* iq, int64_t n_slots, float* H, fl
                 void* hip_stream) {
   (void)workspace;
   int st = check_call(plan, iq, n_slots);
-  if (st != RX_OK) return st;
-  if (n_slots > 0 && (!H || !aligned(H, 8))) return RX_E_INVALID_ARG;
+  if (st != RX_OK || n_slots == 0) return st;
+  if (!H || !aligned(H, 8)) return RX_E_INVALID_ARG;
   if (g && !aligned(g, 4)) return RX_E_INVALID_ARG;
-  if (n_slots == 0) return RX_OK;
   if ((st = check_device(plan)) != RX_OK) return st;
   const rx::LaunchArgs la = launch_args(plan, iq, n_slots, hip_stream);
   float2* H2 = reinterpret_cast<float2*>(H);
@@ -176,11 +175,10 @@ int rx_demod(rx_plan_t plan, const int16_t* iq, const float* H, int64_t n_slots,
              void* workspace, void* hip_stream) {
   (void)workspace;
   int st = check_call(plan, iq, n_slots);
-  if (st != RX_OK) return st;
+  if (st != RX_OK || n_slots == 0) return st;
   if (!xhat && !bits) return RX_E_INVALID_ARG;
-  if (n_slots > 0 && (!H || !aligned(H, 8))) return RX_E_INVALID_ARG;
+  if (!H || !aligned(H, 8)) return RX_E_INVALID_ARG;
   if (xhat && !aligned(xhat, 8)) return RX_E_INVALID_ARG;
-  if (n_slots == 0) return RX_OK;
   if ((st = check_device(plan)) != RX_OK) return st;
   const rx::LaunchArgs la = launch_args(plan, iq, n_slots, hip_stream);
   return hip_status(rx::launch_demod(la, plan->p.combiner == RX_COMB_ZF, reinterpret_cast<const float2*>(H),
@@ -190,12 +188,11 @@ int rx_demod(rx_plan_t plan, const int16_t* iq, const float* H, int64_t n_slots,
 int rx_process_frame(rx_plan_t plan, const int16_t* iq, int64_t n_slots, float* H, float* xhat, uint8_t* bits,
                      void* workspace, void* hip_stream) {
   int st = check_call(plan, iq, n_slots);
-  if (st != RX_OK) return st;
+  if (st != RX_OK || n_slots == 0) return st;
   if (!xhat && !bits) return RX_E_INVALID_ARG;
   if (xhat && !aligned(xhat, 8)) return RX_E_INVALID_ARG;
   if (H && !aligned(H, 8)) return RX_E_INVALID_ARG;
-  if (!H && n_slots > 0 && (!workspace || !aligned(workspace, 256))) return RX_E_INVALID_ARG;
-  if (n_slots == 0) return RX_OK;
+  if (!H && (!workspace || !aligned(workspace, 256))) return RX_E_INVALID_ARG;
   if ((st = check_device(plan)) != RX_OK) return st;
   const rx::LaunchArgs la = launch_args(plan, iq, n_slots, hip_stream);
   float2* Hbuf = reinterpret_cast<float2*>(H ? static_cast<void*>(H) : workspace);
@@ -205,9 +202,8 @@ int rx_process_frame(rx_plan_t plan, const int16_t* iq, int64_t n_slots, float* 
 
 int rx_debug_fft(rx_plan_t plan, const int16_t* iq, int64_t n_slots, float* Y, void* hip_stream) {
   int st = check_call(plan, iq, n_slots);
-  if (st != RX_OK) return st;
-  if (n_slots > 0 && (!Y || !aligned(Y, 8))) return RX_E_INVALID_ARG;
-  if (n_slots == 0) return RX_OK;
+  if (st != RX_OK || n_slots == 0) return st;
+  if (!Y || !aligned(Y, 8)) return RX_E_INVALID_ARG;
   if ((st = check_device(plan)) != RX_OK) return st;
   const rx::LaunchArgs la = launch_args(plan, iq, n_slots, hip_stream);
   return hip_status(rx::launch_fft(la, reinterpret_cast<float2*>(Y)));

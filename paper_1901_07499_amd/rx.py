@@ -39,6 +39,13 @@ class rx_params(ctypes.Structure):
 
 
 def _load() -> ctypes.CDLL:
+    # torch bundles its own HIP runtime under the same SONAME as the system
+    # one; loading torch first makes librx.so bind to that single runtime, so
+    # device pointers and streams handed over by torch are valid in our calls.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1901_07499_amd.build` "
                           "(the receive path has no non-HIP implementation)")

@@ -107,3 +107,13 @@ def test_plan_creation_without_gpu_reports_hip_error():
     p, keep = _p()
     st, plan = rx.rx_plan_create(p)
     assert st == rx.RX_E_HIP and plan is None
+
+
+def test_single_hip_runtime_in_process():
+    # torch and librx.so must share one libamdhip64 (same SONAME, two files on
+    # disk); two copies would give two device contexts and invalid pointers.
+    paths = set()
+    for line in open("/proc/self/maps"):
+        if "libamdhip64" in line:
+            paths.add(line.split()[-1])
+    assert len(paths) == 1, paths

@@ -56,6 +56,49 @@ def algorithmic_bytes(cfg, S: int, part: str) -> int:
     raise ValueError(part)
 
 
+COPY_BYTES = 1 << 30
+
+
+def copy_calibration():
+    """A plain device-to-device copy of COPY_BYTES: reads and writes COPY_BYTES each."""
+    import torch
+    src = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"copied {COPY_BYTES} B x 3")
+
+
+def _counter_per_dispatch(path, kernel_substr, counter):
+    import csv
+    vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(path))
+            if kernel_substr in r["Kernel_Name"] and r["Counter_Name"] == counter]
+    if not vals:
+        raise SystemExit(f"no {counter} for {kernel_substr} in {path}")
+    return sum(vals) / len(vals)
+
+
+def write_traffic(demod_fetch, demod_write, copy_fetch, copy_write):
+    """HBM bytes per demod launch from FETCH_SIZE / WRITE_SIZE (KiB per dispatch),
+    each scaled by COPY_BYTES / (what the counter reads for the reference copy)."""
+    from rxgen import C2
+    cf = _counter_per_dispatch(copy_fetch, "copyBuffer", "FETCH_SIZE") * 1024
+    cw = _counter_per_dispatch(copy_write, "copyBuffer", "WRITE_SIZE") * 1024
+    kf = COPY_BYTES / cf
+    kw = COPY_BYTES / cw
+    df = _counter_per_dispatch(demod_fetch, "demod_kernel", "FETCH_SIZE") * 1024 * kf
+    dw = _counter_per_dispatch(demod_write, "demod_kernel", "WRITE_SIZE") * 1024 * kw
+    rec = {"workload": C2.name, "kernel": "demod_kernel", "kernel_hash": kernel_hash(),
+           "fetch_bytes": df, "write_bytes": dw, "bytes_per_launch": df + dw,
+           "fetch_scale": kf, "write_scale": kw,
+           "algorithmic_bytes_per_launch": algorithmic_bytes(C2, C2.n_slots, "demod")}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,7 +107,17 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-quality", action="store_true", help="skip the 20 dB quality figures")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device-to-device copy (reference for the traffic counters)")
+    ap.add_argument("--write-traffic", nargs=4, metavar=("DEMOD_FETCH", "DEMOD_WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="turn four rocprofv3 --pmc counter_collection.csv files into " + TRAFFIC_FILE)
     args = ap.parse_args()
+    if args.write_traffic:
+        write_traffic(*args.write_traffic)
+        return
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this receive path shards by slot with no exchange, "
               "so multi-GPU throughput is N x the one-GPU figure; run with --gpus 1", file=sys.stderr)

@@ -13,8 +13,8 @@
 // Pass with radix R after stride NS (product of the earlier radices):
 // butterfly j in [0, N/R) takes x[j + r*N/R], r = 0..R-1, multiplies element r
 // by W^(r*(j mod NS)) with W = exp(-2 pi i / (NS*R)), takes the R-point DFT and
-// stores output r at (j / NS)*NS*R + (j mod NS) + r*NS.  After the last pass
-// the spectrum is in natural order.
+// stores output r at (j / NS)*NS*R + (j mod NS) + r*NS.  The last pass keeps
+// its outputs in registers: lane li ends with bins li + L*q, q = 0..P-1.
 //
 // The transform computed is Y[k] = sum_n y[n] exp(-2 pi i k n / N) (forward,
 // unscaled) -- the FFT taken after CP removal on every antenna (paper
@@ -23,6 +23,8 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 namespace rx {
 
@@ -161,69 +163,194 @@ struct FftShape {
   static_assert(N >= 64 && N <= 2048 && (N & (N - 1)) == 0, "N must be a power of two in [64, 2048]");
 };
 
-// One Stockham pass.  On entry (FIRST) v holds this lane's inputs
-// v[m*R + r] = x[j_m + r*N/R], j_m = li + L*m; otherwise they are gathered
-// from `buf`.  Output goes to `buf` (padded indexing).
-template <int N, int R, int NS, bool FIRST>
-__device__ __forceinline__ void stockham_pass(float2 (&v)[FftShape<N>::P], float2* buf, int li,
-                                              const float2* __restrict__ tw) {
+// Radix schedule per N: the first pass is always radix 16 (16 points of one
+// transform per lane, loaded straight from memory); later radices are chosen
+// to keep the number of distinct twiddles per lane small.
+template <int N>
+struct Radices;
+template <> struct Radices<64>   { static constexpr int R1 = 16, R2 = 4, R3 = 0; };
+template <> struct Radices<128>  { static constexpr int R1 = 16, R2 = 8, R3 = 0; };
+template <> struct Radices<256>  { static constexpr int R1 = 16, R2 = 16, R3 = 0; };
+template <> struct Radices<512>  { static constexpr int R1 = 16, R2 = 2, R3 = 16; };
+template <> struct Radices<1024> { static constexpr int R1 = 16, R2 = 4, R3 = 16; };
+template <> struct Radices<2048> { static constexpr int R1 = 16, R2 = 8, R3 = 16; };
+
+// Twiddles of one pass (radix R after stride NS) for this lane's butterflies
+// j_m = li + L*m: element r of butterfly m is multiplied by
+// exp(-2 pi i r (j_m mod NS) / (NS R)).  When L is a multiple of NS every
+// butterfly of the lane shares one set.  Loaded once per kernel into VGPRs.
+template <int N, int R, int NS>
+struct PassTwiddles {
+  static constexpr int P = FftShape<N>::P, L = FftShape<N>::L, NB = R > 0 ? P / R : 1;
+  static constexpr bool kShared = (NS == 1) || (L % NS == 0);
+  static constexpr int kSets = kShared ? 1 : NB;
+  static constexpr int kCount = (NS == 1 || R == 0) ? 1 : kSets * (R - 1);
+  float2 w[kCount];
+  __device__ __forceinline__ void load(const float2* __restrict__ tw, int li) {
+    if constexpr (NS > 1 && R > 0) {
+#pragma unroll
+      for (int s = 0; s < kSets; s++) {
+        const int step = ((li + L * s) & (NS - 1)) * (N / (NS * R));
+#pragma unroll
+        for (int r = 1; r < R; r++) w[s * (R - 1) + r - 1] = tw[step * r];
+      }
+    }
+  }
+  __device__ __forceinline__ float2 get(int m, int r) const { return w[(kShared ? 0 : m) * (R - 1) + r - 1]; }
+};
+
+// Twiddles of the last pass kept in LDS instead of VGPRs: entry
+// [(s*(R-1) + r-1)*L + li] = exp(-2 pi i r ((li + L s) mod NS) / (NS R)).
+// Lanes read consecutive entries (no bank conflicts); every transform of the
+// wavefront reads the same values.
+template <int N, int R, int NS>
+struct LdsTwiddles {
+  static constexpr int P = FftShape<N>::P, L = FftShape<N>::L, NB = R > 0 ? P / R : 1;
+  static constexpr bool kShared = (NS == 1) || (L % NS == 0);
+  static constexpr int kSets = kShared ? 1 : NB;
+  static constexpr int kCount = (NS == 1 || R == 0) ? 1 : kSets * (R - 1) * L;  // float2 entries
+  const float2* tab;
+  int li;
+  // Cooperative fill by the whole workgroup (caller synchronises afterwards).
+  static __device__ __forceinline__ void fill(float2* tab, const float2* __restrict__ tw, int tid, int nthreads) {
+    if constexpr (NS > 1 && R > 0) {
+      for (int e = tid; e < kCount; e += nthreads) {
+        const int lane = e % L, sr = e / L, s = sr / (R - 1), r = sr % (R - 1) + 1;
+        const int step = ((lane + L * s) & (NS - 1)) * (N / (NS * R));
+        tab[e] = tw[step * r];
+      }
+    }
+  }
+  __device__ __forceinline__ float2 get(int m, int r) const { return tab[((kShared ? 0 : m) * (R - 1) + r - 1) * L + li]; }
+};
+
+#ifndef RX_LAST_TWIDDLES_IN_LDS
+#define RX_LAST_TWIDDLES_IN_LDS 1
+#endif
+
+template <int N>
+struct FftTwiddles {
+  using Rd = Radices<N>;
+  static constexpr bool kLdsLast = RX_LAST_TWIDDLES_IN_LDS && Rd::R3 > 0;
+  using P3Regs = PassTwiddles<N, Rd::R3, Rd::R1 * Rd::R2>;
+  using P3Lds = LdsTwiddles<N, Rd::R3, Rd::R1 * Rd::R2>;
+  static constexpr int kLdsFloat2 = kLdsLast ? P3Lds::kCount : 0;  // LDS table size
+  PassTwiddles<N, Rd::R2, Rd::R1> p2;
+  typename std::conditional<kLdsLast, P3Lds, P3Regs>::type p3;
+  // lds_tab: the filled table (only read when kLdsLast)
+  __device__ __forceinline__ void load(const float2* __restrict__ tw, int li, const float2* lds_tab = nullptr) {
+    p2.load(tw, li);
+    if constexpr (kLdsLast) {
+      p3.tab = lds_tab;
+      p3.li = li;
+    } else if constexpr (Rd::R3 > 0) {
+      p3.load(tw, li);
+    }
+  }
+};
+
+// One Stockham pass over C independent transforms held by the lane (C > 1
+// gives the scheduler independent work to overlap with LDS latency).  With
+// FIRST, v[c] already holds this lane's inputs v[c][m*R + r] = x[j_m + r*N/R],
+// j_m = li + L*m; otherwise they are gathered from buf[c].  Output goes to
+// buf[c] (padded indexing) unless LAST, where it stays in v (fft_in_regs).
+template <int N, int R, int NS, bool FIRST, bool LAST, int C, typename TW>
+__device__ __forceinline__ void stockham_pass(float2 (&v)[C][FftShape<N>::P], float2* const (&buf)[C], int li,
+                                              const TW& tw) {
   constexpr int P = FftShape<N>::P;
   constexpr int L = FftShape<N>::L;
   constexpr int NB = P / R;
   static_assert(P % R == 0, "radix must divide the points per lane");
   if constexpr (!FIRST) {
+    const int pli = pad(li);
 #pragma unroll
-    for (int m = 0; m < NB; m++) {
-      const int j = li + L * m;
+    for (int c = 0; c < C; c++)
 #pragma unroll
-      for (int r = 0; r < R; r++) v[m * R + r] = buf[pad(j + r * (N / R))];
-    }
+      for (int m = 0; m < NB; m++)
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          const int k = L * m + r * (N / R);
+          v[c][m * R + r] = buf[c][(k % 16 == 0) ? pli + k + k / 16 : pad(li + k)];
+        }
     wave_fence();  // every lane's reads happen before any lane's writes
   }
 #pragma unroll
-  for (int m = 0; m < NB; m++) {
-    const int j = li + L * m;
-    if constexpr (NS > 1) {
-      const int jm = j & (NS - 1);
-      const int step = jm * (N / (NS * R));
+  for (int c = 0; c < C; c++)
 #pragma unroll
-      for (int r = 1; r < R; r++) v[m * R + r] = cmul(v[m * R + r], tw[step * r]);
+    for (int m = 0; m < NB; m++) {
+      const int j = li + L * m;
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; r++) v[c][m * R + r] = cmul(v[c][m * R + r], tw.get(m, r));
+      }
+      dft<R>(v[c], m * R);
+      if constexpr (!LAST) {
+        const int o = (j / NS) * NS * R + (j & (NS - 1));
+        const int po = pad(o);
+        const bool o16 = (NS == 1) && (R == 16);  // o = 16 j
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          const int k = r * NS;
+          buf[c][(k % 16 == 0) ? po + k + k / 16 : (o16 ? po + k : pad(o + k))] = v[c][m * R + r];
+        }
+      }
     }
-    dft<R>(v, m * R);
-    const int o = (j / NS) * NS * R + (j & (NS - 1));
-#pragma unroll
-    for (int r = 0; r < R; r++) buf[pad(o + r * NS)] = v[m * R + r];
-  }
-  wave_fence();
+  if constexpr (!LAST) wave_fence();
 }
 
-// Whole transform: inputs in v (first-pass order), spectrum left in `buf` in
-// natural order (padded indexing).  `tw[k]` = exp(-2 pi i k / N), k < N.
+// Whole transform of C symbols.  Inputs in v (first-pass order).  On return
+// the spectra are in v: the last pass has stride NS = N / R and one output
+// per butterfly j = li + L*m and r, at bin j + NS*r = li + L*q with
+// q = m + NB*r, so the lane holds bins k = li + L*q, q = 0..P-1, in
+// v[c][Spectrum<N>::reg(q)].  buf[c] is left holding the previous pass's
+// data; the caller fences before writing it again.
 template <int N>
-__device__ __forceinline__ void fft_to_lds(float2 (&v)[FftShape<N>::P], float2* buf, int li,
-                                           const float2* __restrict__ tw) {
-  if constexpr (N == 64) {
-    stockham_pass<N, 16, 1, true>(v, buf, li, tw);
-    stockham_pass<N, 4, 16, false>(v, buf, li, tw);
-  } else if constexpr (N == 128) {
-    stockham_pass<N, 16, 1, true>(v, buf, li, tw);
-    stockham_pass<N, 8, 16, false>(v, buf, li, tw);
-  } else if constexpr (N == 256) {
-    stockham_pass<N, 16, 1, true>(v, buf, li, tw);
-    stockham_pass<N, 16, 16, false>(v, buf, li, tw);
-  } else if constexpr (N == 512) {
-    stockham_pass<N, 16, 1, true>(v, buf, li, tw);
-    stockham_pass<N, 8, 16, false>(v, buf, li, tw);
-    stockham_pass<N, 4, 128, false>(v, buf, li, tw);
-  } else if constexpr (N == 1024) {
-    stockham_pass<N, 16, 1, true>(v, buf, li, tw);
-    stockham_pass<N, 16, 16, false>(v, buf, li, tw);
-    stockham_pass<N, 4, 256, false>(v, buf, li, tw);
-  } else if constexpr (N == 2048) {
-    stockham_pass<N, 16, 1, true>(v, buf, li, tw);
-    stockham_pass<N, 16, 16, false>(v, buf, li, tw);
-    stockham_pass<N, 8, 256, false>(v, buf, li, tw);
+struct Spectrum {
+  using Rd = Radices<N>;
+  static constexpr int R = Rd::R3 > 0 ? Rd::R3 : Rd::R2;  // last radix
+  static constexpr int NB = FftShape<N>::P / R;
+  static constexpr int reg(int q) { return (q % NB) * R + q / NB; }
+};
+
+// First pass only (inputs in registers, output to LDS).
+template <int N, int C>
+__device__ __forceinline__ void fft_first_pass(float2 (&v)[C][FftShape<N>::P], float2* const (&buf)[C], int li) {
+  using Rd = Radices<N>;
+  const PassTwiddles<N, Rd::R1, 1> none{};
+  stockham_pass<N, Rd::R1, 1, true, false, C>(v, buf, li, none);
+}
+
+// The passes after the first; the spectrum ends in v.
+template <int N, int C>
+__device__ __forceinline__ void fft_rest(float2 (&v)[C][FftShape<N>::P], float2* const (&buf)[C], int li,
+                                         const FftTwiddles<N>& tw) {
+  using Rd = Radices<N>;
+  if constexpr (Rd::R3 > 0) {
+    stockham_pass<N, Rd::R2, Rd::R1, false, false, C>(v, buf, li, tw.p2);
+    stockham_pass<N, Rd::R3, Rd::R1 * Rd::R2, false, true, C>(v, buf, li, tw.p3);
+  } else {
+    stockham_pass<N, Rd::R2, Rd::R1, false, true, C>(v, buf, li, tw.p2);
   }
+}
+
+template <int N, int C>
+__device__ __forceinline__ void fft_in_regs(float2 (&v)[C][FftShape<N>::P], float2* const (&buf)[C], int li,
+                                            const FftTwiddles<N>& tw) {
+  fft_first_pass<N, C>(v, buf, li);
+  fft_rest<N, C>(v, buf, li, tw);
+}
+
+// Single-transform form.
+template <int N>
+__device__ __forceinline__ void fft_in_regs(float2 (&v)[FftShape<N>::P], float2* buf, int li,
+                                            const FftTwiddles<N>& tw) {
+  float2 vv[1][FftShape<N>::P];
+#pragma unroll
+  for (int i = 0; i < FftShape<N>::P; i++) vv[0][i] = v[i];
+  float2* const b[1] = {buf};
+  fft_in_regs<N, 1>(vv, b, li, tw);
+#pragma unroll
+  for (int i = 0; i < FftShape<N>::P; i++) v[i] = vv[0][i];
 }
 
 // int16 I/Q packed in one dword (I in the low half) -> complex float, exact.
@@ -232,7 +359,9 @@ __device__ __forceinline__ float2 iq_to_float(uint32_t w) {
 }
 
 // Load this lane's first-pass inputs for one symbol: x[n] = sample CP + n of
-// the record starting at `rec` (dword per complex sample).
+// the record starting at `rec` (one dword per complex sample).  The loads
+// are unconditional (the caller passes a valid record); lanes whose
+// transform slot is unused get zeros afterwards, without branching.
 template <int N>
 __device__ __forceinline__ void load_symbol(uint32_t (&raw)[FftShape<N>::P], const uint32_t* __restrict__ rec,
                                             int li, bool valid) {
@@ -243,8 +372,11 @@ __device__ __forceinline__ void load_symbol(uint32_t (&raw)[FftShape<N>::P], con
 #pragma unroll
   for (int m = 0; m < NB; m++)
 #pragma unroll
-    for (int r = 0; r < R; r++)
-      raw[m * R + r] = valid ? __builtin_nontemporal_load(rec + li + L * m + r * (N / R)) : 0u;
+    for (int r = 0; r < R; r++) raw[m * R + r] = __builtin_nontemporal_load(rec + li + L * m + r * (N / R));
+  if constexpr (FftShape<N>::F > 1) {
+#pragma unroll
+    for (int i = 0; i < P; i++) raw[i] = valid ? raw[i] : 0u;
+  }
 }
 
 template <int N>

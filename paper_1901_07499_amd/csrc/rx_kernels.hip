@@ -2,14 +2,22 @@
 //
 // estimate_kernel  pilot symbol of every (slot, antenna): int16 load with the
 //                  CP skipped, FFT, LS divide by the pilot (paper Sec. II-B;
-//                  Sec. II-C, LS paragraph), H written in subcarrier order.
+//                  Sec. II-C, LS paragraph), H written in subcarrier order
+//                  straight from the FFT's output registers.
 // demod_kernel     one workgroup per (slot, data symbol): its wavefronts split
 //                  the antennas, FFT each antenna's symbol and accumulate the
-//                  MRC sums conj(H) Y and |H|^2 per used subcarrier in VGPRs
-//                  (paper Sec. II-C, MRC paragraph); a fixed-order cross-wave
-//                  reduction in LDS follows, then x = z / g, hard decisions and
-//                  packed bits.  ZF (one user) instead weights every antenna by
-//                  conj(H)/g, with g summed first.
+//                  MRC sums conj(H) Y and |H|^2 of the used subcarriers from
+//                  the FFT's output registers (paper Sec. II-C, MRC
+//                  paragraph); a fixed-order cross-wave reduction in LDS
+//                  follows, then x = z / g, hard decisions and packed bits.
+//                  ZF (one user) instead weights every antenna by conj(H)/g,
+//                  with g summed first.
+//
+// After the FFT a lane holds bins li + L*q, q = 0..P-1 (see rx_fft.hpp).  The
+// used subcarriers are the bins within U/2 of DC, so only the registers
+// q < QH and q >= P - QH (QH = ceil((U/2 + 1) / L)) can hold one: the demod
+// kernel is instantiated for a window of 2*QH registers and the other FFT
+// outputs are never computed.
 // g_kernel         g[s][d] = sum_a |H[s][a][d]|^2 for the estimate call.
 // fft_kernel       CP removal + FFT only (validation of the FFT stage).
 //
@@ -21,10 +29,34 @@
 #include "rx_fft.hpp"
 #include "rx_launch.h"
 
+// Tuning constants (compile time): wavefronts per demod workgroup and the
+// minimum wavefronts per SIMD the demod kernel's register budget must allow.
+#ifndef RX_DEMOD_WAVES
+#define RX_DEMOD_WAVES 4
+#endif
+#ifndef RX_DEMOD_MIN_WAVES_PER_EU
+#define RX_DEMOD_MIN_WAVES_PER_EU 1
+#endif
+// Symbols a demod wavefront transforms side by side per loop iteration when
+// one transform fills the wavefront (N >= 1024): independent work that hides
+// the LDS round trips between FFT passes.
+#ifndef RX_DEMOD_ILP
+#define RX_DEMOD_ILP 1
+#endif
+// How many jobs ahead a demod wavefront requests its input samples (1 or 2).
+#ifndef RX_DEMOD_PREFETCH
+#define RX_DEMOD_PREFETCH 1
+#endif
+
 namespace rx {
 
-__device__ __forceinline__ int bin_of(int d, int n, int u) {
-  return d < (u >> 1) ? d + n - (u >> 1) : d - (u >> 1) + 1;
+// Used-subcarrier index of FFT bin k (0 <= k < n), or -1 when the bin is not
+// used: bins 1..U/2 are subcarriers U/2..U-1, bins n-U/2..n-1 are 0..U/2-1.
+__device__ __forceinline__ int sub_of_bin(int k, int n, int u) {
+  const int h = u >> 1;
+  if (k >= 1 && k <= h) return k - 1 + h;
+  if (k >= n - h) return k - (n - h);
+  return -1;
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8).
@@ -50,32 +82,41 @@ __global__ __launch_bounds__(64 * W) void estimate_kernel(const uint32_t* __rest
   const int64_t s = blockIdx.x / blocks_per_slot;
   const int blk = blockIdx.x % blocks_per_slot;
   const int a0 = (blk * W + wave) * Sh::F;
-  if (a0 >= A) return;  // no workgroup barrier in this kernel
+  __shared__ float2 twtab[FftTwiddles<N>::kLdsFloat2 > 0 ? FftTwiddles<N>::kLdsFloat2 : 1];
+  if constexpr (FftTwiddles<N>::kLdsLast) {
+    FftTwiddles<N>::P3Lds::fill(twtab, tw, threadIdx.x, blockDim.x);
+    __syncthreads();
+  }
+  if (a0 >= A) return;  // no workgroup barrier below
   const int a = a0 + f;
   const bool valid = a < A;
   const uint32_t* rec = iq + ((s * T) * A + (valid ? a : a0)) * (int64_t)(N + CP) + CP;
   uint32_t raw[Sh::P];
   load_symbol<N>(raw, rec, li, valid);
+  FftTwiddles<N> twr;
+  twr.load(tw, li, twtab);
   float2 v[Sh::P];
   unpack_symbol<N>(v, raw);
-  float2* slot = lds + (wave * Sh::F) * Lds<N>::kSlot;
-  fft_to_lds<N>(v, slot + f * Lds<N>::kSlot, li, tw);
-  for (int ff = 0; ff < Sh::F; ff++) {
-    const int aa = a0 + ff;
-    if (aa >= A) break;
-    const float2* y = slot + ff * Lds<N>::kSlot;
-    float2* hrow = H + (s * A + aa) * (int64_t)U;
-    for (int d = lane; d < U; d += 64) hrow[d] = cmul(y[pad(bin_of(d, N, U))], pf[d]);
+  fft_in_regs<N>(v, lds + (wave * Sh::F + f) * Lds<N>::kSlot, li, twr);
+  if (valid) {
+    float2* hrow = H + (s * A + a) * (int64_t)U;
+#pragma unroll
+    for (int q = 0; q < Sh::P; q++) {
+      const int d = sub_of_bin(li + Sh::L * q, N, U);
+      if (d >= 0) hrow[d] = cmul(v[Spectrum<N>::reg(q)], pf[d]);
+    }
   }
 }
 
 // ------------------------------------------------------------------ demod
-template <int N, int NI, int W, bool ZF>
-__global__ __launch_bounds__(64 * W) void demod_kernel(const uint32_t* __restrict__ iq, int64_t S, int A, int T,
-                                                       int CP, int U, int B, const float2* __restrict__ tw,
-                                                       const float2* __restrict__ H, float2* __restrict__ xhat,
-                                                       uint8_t* __restrict__ bits) {
+template <int N, int QH, int W, bool ZF>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(RX_DEMOD_MIN_WAVES_PER_EU)))
+void demod_kernel(const uint32_t* __restrict__ iq, int64_t S, int A, int T, int CP, int U, int B,
+                  const float2* __restrict__ tw, const float2* __restrict__ H, float2* __restrict__ xhat,
+                  uint8_t* __restrict__ bits) {
   using Sh = FftShape<N>;
+  constexpr int NI = 2 * QH;  // spectrum registers that can hold a used subcarrier
+  static_assert(NI <= Sh::P, "window wider than the lane's spectrum");
   extern __shared__ float2 lds[];
   const int Td = T - 1;
   const int64_t item = xcd_remap(blockIdx.x, S * Td);
@@ -85,12 +126,20 @@ __global__ __launch_bounds__(64 * W) void demod_kernel(const uint32_t* __restric
   const int f = lane / Sh::L, li = lane % Sh::L;
   const float2* Hs = H + s * A * (int64_t)U;
 
-  int kofs[NI];
-#pragma unroll
-  for (int i = 0; i < NI; i++) {
-    const int d = lane + 64 * i;
-    kofs[i] = pad(bin_of(d < U ? d : 0, N, U));
-  }
+  // Window register i holds spectrum register q(i) = i (i < QH, bins
+  // li + L*i above DC) or P - NI + i (bins below N, i.e. negative
+  // frequencies).  Its subcarrier is li + doff(i) when wok(i).  Channel
+  // loads use that index clamped into [0, U): a lane whose bin is unused
+  // reads some in-bounds value and its (meaningless) sum is never stored, so
+  // the loop needs no per-lane branches.
+  const int hU = U >> 1;
+  auto qof = [](int i) { return i < QH ? i : Sh::P - NI + i; };
+  auto doff = [&](int i) { return Sh::L * qof(i) + (i < QH ? hU - 1 : hU - N); };
+  auto wok = [&](int i) {
+    const int k = li + Sh::L * qof(i);
+    return i < QH ? (k >= 1 && k <= hU) : (k >= N - hU);
+  };
+  auto dcl = [&](int i) { return min(max(li + doff(i), 0), U - 1); };
   float2 z[NI];
   float g[NI];
 #pragma unroll
@@ -103,63 +152,113 @@ __global__ __launch_bounds__(64 * W) void demod_kernel(const uint32_t* __restric
     for (int a = 0; a < A; a++) {
 #pragma unroll
       for (int i = 0; i < NI; i++) {
-        const int d = lane + 64 * i;
-        if (d < U) {
-          const float2 h = Hs[(int64_t)a * U + d];
-          g[i] = fmaf(h.x, h.x, fmaf(h.y, h.y, g[i]));
-        }
+        const float2 h = Hs[(int64_t)a * U + dcl(i)];
+        g[i] = fmaf(h.x, h.x, fmaf(h.y, h.y, g[i]));
       }
     }
 #pragma unroll
     for (int i = 0; i < NI; i++) g[i] = g[i] > 0.f ? 1.0f / g[i] : 0.f;  // now 1/g
   }
 
-  float2* slot = lds + (wave * Sh::F) * Lds<N>::kSlot;
+  // C symbols (antennas) per lane per iteration; antenna of lane group f and
+  // slot c in job J: J*F*C + c*F + f.  Job J = iteration * W + wave.
+  constexpr int C = Sh::F == 1 ? RX_DEMOD_ILP : 1;
+  float2* bufs[C];
+#pragma unroll
+  for (int c = 0; c < C; c++) bufs[c] = lds + ((wave * C + c) * Sh::F + f) * Lds<N>::kSlot;
+  float2* const(&buf)[C] = bufs;
   const int64_t sym_base = ((s * T + t) * A) * (int64_t)(N + CP) + CP;
-  for (int a0 = wave * Sh::F; a0 < A; a0 += W * Sh::F) {
-    const int a = a0 + f;
-    const bool valid = a < A;
-    uint32_t raw[Sh::P];
-    load_symbol<N>(raw, iq + sym_base + (int64_t)(valid ? a : a0) * (N + CP), li, valid);
-    float2 v[Sh::P];
-    unpack_symbol<N>(v, raw);
-    fft_to_lds<N>(v, slot + f * Lds<N>::kSlot, li, tw);
-    for (int ff = 0; ff < Sh::F; ff++) {
-      const int aa = a0 + ff;
-      if (aa >= A) break;
-      const float2* y = slot + ff * Lds<N>::kSlot;
-      const float2* hrow = Hs + (int64_t)aa * U;
+  __shared__ float2 twtab[FftTwiddles<N>::kLdsFloat2 > 0 ? FftTwiddles<N>::kLdsFloat2 : 1];
+  if constexpr (FftTwiddles<N>::kLdsLast) {
+    FftTwiddles<N>::P3Lds::fill(twtab, tw, threadIdx.x, blockDim.x);
+    __syncthreads();
+  }
+  FftTwiddles<N> twr;
+  twr.load(tw, li, twtab);
+  // Software pipeline over this wavefront's antennas: each job's samples are
+  // requested D jobs ahead.
+  constexpr int JA = Sh::F * C;  // antennas per job
+  const int a_step = W * JA;
+  int a0 = wave * JA;
+  constexpr int D = RX_DEMOD_PREFETCH;
+  static_assert(D == 1 || D == 2, "prefetch depth 1 or 2");
+  auto request = [&](uint32_t (&dst)[C][Sh::P], int aj) {
+#pragma unroll
+    for (int c = 0; c < C; c++) {
+      const int a = aj + c * Sh::F + f;
+      load_symbol<N>(dst[c], iq + sym_base + (int64_t)(a < A ? a : aj) * (N + CP), li, a < A);
+    }
+  };
+  // One job: its samples are in `cur`; once unpacked, `cur` is refilled with
+  // the samples of the job D steps ahead (after this job's channel rows were
+  // requested: vector loads complete in issue order, so waiting for the rows
+  // does not wait for those later sample loads).
+  auto job = [&](uint32_t (&cur)[C][Sh::P], int aj) {
+    float2 v[C][Sh::P];
+#pragma unroll
+    for (int c = 0; c < C; c++) unpack_symbol<N>(v[c], cur[c]);
+    fft_first_pass<N, C>(v, buf, li);
+    float2 h[C][NI];
+#pragma unroll
+    for (int c = 0; c < C; c++) {
+      const int a = aj + c * Sh::F + f;
+      const bool ok = a < A;
+      const float2* hrow = Hs + (int64_t)(ok ? a : aj) * U;
 #pragma unroll
       for (int i = 0; i < NI; i++) {
-        const int d = lane + 64 * i;
-        if (d < U) {
-          const float2 yy = y[kofs[i]];
-          const float2 h = hrow[d];
-          if constexpr (ZF) {
-            const float2 w = make_float2(h.x * g[i], -h.y * g[i]);  // conj(h) / g
-            z[i].x = fmaf(w.x, yy.x, fmaf(-w.y, yy.y, z[i].x));
-            z[i].y = fmaf(w.x, yy.y, fmaf(w.y, yy.x, z[i].y));
-          } else {
-            z[i].x = fmaf(h.x, yy.x, fmaf(h.y, yy.y, z[i].x));  // conj(h) * y
-            z[i].y = fmaf(h.x, yy.y, fmaf(-h.y, yy.x, z[i].y));
-            g[i] = fmaf(h.x, h.x, fmaf(h.y, h.y, g[i]));
-          }
-        }
+        const float2 hv = hrow[dcl(i)];
+        // a lane group whose antenna is past A must add nothing to its row
+        h[c][i] = (Sh::F == 1 || ok) ? hv : make_float2(0.f, 0.f);
       }
     }
+    if (aj + D * a_step < A) request(cur, aj + D * a_step);
+    fft_rest<N, C>(v, buf, li, twr);
+#pragma unroll
+    for (int c = 0; c < C; c++)
+#pragma unroll
+      for (int i = 0; i < NI; i++) {
+        const int q = i < QH ? i : Sh::P - NI + i;
+        const float2 y = v[c][Spectrum<N>::reg(q)];
+        const float2 hh = h[c][i];  // zero for antennas past A
+        if constexpr (ZF) {
+          const float2 w = make_float2(hh.x * g[i], -hh.y * g[i]);  // conj(h) / g
+          z[i].x = fmaf(w.x, y.x, fmaf(-w.y, y.y, z[i].x));
+          z[i].y = fmaf(w.x, y.y, fmaf(w.y, y.x, z[i].y));
+        } else {
+          z[i].x = fmaf(hh.x, y.x, fmaf(hh.y, y.y, z[i].x));  // conj(h) * y
+          z[i].y = fmaf(hh.x, y.y, fmaf(-hh.y, y.x, z[i].y));
+          g[i] = fmaf(hh.x, hh.x, fmaf(hh.y, hh.y, g[i]));
+        }
+      }
     wave_fence();  // this job's LDS reads precede the next job's writes
+  };
+  // D sample buffers used round robin by a loop unrolled D times, so no
+  // register copies (which would wait for the loads) are needed.
+  uint32_t nxt[D][C][Sh::P];
+#pragma unroll
+  for (int d = 0; d < D; d++)
+    if (a0 + d * a_step < A) request(nxt[d], a0 + d * a_step);
+  for (; a0 < A; a0 += D * a_step) {
+    job(nxt[0], a0);
+    if constexpr (D == 2) {
+      if (a0 + a_step < A) job(nxt[1], a0 + a_step);
+    }
   }
 
-  // Cross-wave reduction, fixed order over waves.
+  // Cross-wave reduction in a fixed order: row = wave * F + f holds the
+  // partial sums of one group of antennas for every used subcarrier (each
+  // subcarrier sits in exactly one lane of a transform's lane group; h = 0
+  // made invalid antennas contribute zeros).
+  constexpr int ROWS = W * Sh::F;
   __syncthreads();
-  float2* rz = lds;                                   // [W][U]
-  float* rg = reinterpret_cast<float*>(lds + W * U);  // [W][U]
+  float2* rz = lds;                                      // [ROWS][U]
+  float* rg = reinterpret_cast<float*>(lds + ROWS * U);  // [ROWS][U]
+  const int row = wave * Sh::F + f;
 #pragma unroll
   for (int i = 0; i < NI; i++) {
-    const int d = lane + 64 * i;
-    if (d < U) {
-      rz[wave * U + d] = z[i];
-      if constexpr (!ZF) rg[wave * U + d] = g[i];
+    if (wok(i)) {
+      rz[row * U + li + doff(i)] = z[i];
+      if constexpr (!ZF) rg[row * U + li + doff(i)] = g[i];
     }
   }
   __syncthreads();
@@ -168,15 +267,14 @@ __global__ __launch_bounds__(64 * W) void demod_kernel(const uint32_t* __restric
   const int64_t out_row = s * Td + (t - 1);
   const float c16 = 3.16227766016837933f;  // sqrt(10)
   const float c64 = 6.48074069840786023f;  // sqrt(42)
-  for (int q = threadIdx.x; 4 * q < U; q += 64 * W) {
-    const int nsym = min(4, U - 4 * q);
+  for (int qd = threadIdx.x; 4 * qd < U; qd += 64 * W) {
+    const int nsym = min(4, U - 4 * qd);
     uint32_t acc = 0;  // bits of up to 4 symbols, MSB-first
     for (int e = 0; e < nsym; e++) {
-      const int d = 4 * q + e;
+      const int d = 4 * qd + e;
       float2 zz = make_float2(0.f, 0.f);
       float gg = 0.f;
-#pragma unroll
-      for (int w = 0; w < W; w++) {
+      for (int w = 0; w < ROWS; w++) {
         const float2 p = rz[w * U + d];
         zz.x += p.x;
         zz.y += p.y;
@@ -206,8 +304,8 @@ __global__ __launch_bounds__(64 * W) void demod_kernel(const uint32_t* __restric
       for (int j = 0; j < B / 2; j++) acc = (acc << 2) | (br[j] << 1) | bi[j];
     }
     if (bits) {
-      const int nbits = nsym * B;  // a multiple of 8
-      uint8_t* o = bits + out_row * row_bytes + (q * B) / 2;  // 4 symbols = B/2 bytes
+      const int nbits = nsym * B;                                // a multiple of 8
+      uint8_t* o = bits + out_row * row_bytes + (qd * B) / 2;   // 4 symbols = B/2 bytes
       for (int byte = 0; byte < nbits / 8; byte++) o[byte] = (uint8_t)(acc >> (nbits - 8 * (byte + 1)));
     }
   }
@@ -240,29 +338,33 @@ __global__ __launch_bounds__(64 * W) void fft_kernel(const uint32_t* __restrict_
   const int64_t st = blockIdx.x / blocks_per_sym;  // s * T + t
   const int blk = blockIdx.x % blocks_per_sym;
   const int a0 = (blk * W + wave) * Sh::F;
-  if (a0 >= A) return;
+  __shared__ float2 twtab[FftTwiddles<N>::kLdsFloat2 > 0 ? FftTwiddles<N>::kLdsFloat2 : 1];
+  if constexpr (FftTwiddles<N>::kLdsLast) {
+    FftTwiddles<N>::P3Lds::fill(twtab, tw, threadIdx.x, blockDim.x);
+    __syncthreads();
+  }
+  if (a0 >= A) return;  // no workgroup barrier below
   const int a = a0 + f;
   const bool valid = a < A;
   const uint32_t* rec = iq + (st * A + (valid ? a : a0)) * (int64_t)(N + CP) + CP;
   uint32_t raw[Sh::P];
   load_symbol<N>(raw, rec, li, valid);
+  FftTwiddles<N> twr;
+  twr.load(tw, li, twtab);
   float2 v[Sh::P];
   unpack_symbol<N>(v, raw);
-  float2* slot = lds + (wave * Sh::F) * Lds<N>::kSlot;
-  fft_to_lds<N>(v, slot + f * Lds<N>::kSlot, li, tw);
-  for (int ff = 0; ff < Sh::F; ff++) {
-    const int aa = a0 + ff;
-    if (aa >= A) break;
-    const float2* y = slot + ff * Lds<N>::kSlot;
-    float2* out = Y + (st * A + aa) * (int64_t)N;
-    for (int k = lane; k < N; k += 64) out[k] = y[pad(k)];
+  fft_in_regs<N>(v, lds + (wave * Sh::F + f) * Lds<N>::kSlot, li, twr);
+  if (valid) {
+    float2* out = Y + (st * A + a) * (int64_t)N;
+#pragma unroll
+    for (int q = 0; q < Sh::P; q++) out[li + Sh::L * q] = v[Spectrum<N>::reg(q)];
   }
 }
 
 // ------------------------------------------------------------------ launchers
 namespace {
 constexpr int kWavesEst = 4;
-constexpr int kWavesDemod = 4;
+constexpr int kWavesDemod = RX_DEMOD_WAVES;
 constexpr int kWavesFft = 4;
 
 template <int N>
@@ -304,40 +406,35 @@ hipError_t fft_n(const LaunchArgs& la, float2* Y) {
   return hipGetLastError();
 }
 
-template <int N, int NI, bool ZF>
-hipError_t demod_ni(const LaunchArgs& la, const float2* H, float2* xhat, uint8_t* bits) {
+template <int N, int QH, bool ZF>
+hipError_t demod_qh(const LaunchArgs& la, const float2* H, float2* xhat, uint8_t* bits) {
   const int64_t grid = la.S * (la.T - 1);
-  size_t lds = fft_lds_bytes<N>(kWavesDemod);
-  const size_t red = (size_t)kWavesDemod * la.U * (sizeof(float2) + sizeof(float));
+  constexpr int C = FftShape<N>::F == 1 ? RX_DEMOD_ILP : 1;
+  size_t lds = fft_lds_bytes<N>(kWavesDemod) * C;
+  const size_t red = (size_t)kWavesDemod * FftShape<N>::F * la.U * (sizeof(float2) + sizeof(float));
   if (red > lds) lds = red;
-  hipError_t e = allow_lds(demod_kernel<N, NI, kWavesDemod, ZF>, lds);
+  hipError_t e = allow_lds(demod_kernel<N, QH, kWavesDemod, ZF>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((demod_kernel<N, NI, kWavesDemod, ZF>), dim3((unsigned)grid), dim3(64 * kWavesDemod), lds,
+  hipLaunchKernelGGL((demod_kernel<N, QH, kWavesDemod, ZF>), dim3((unsigned)grid), dim3(64 * kWavesDemod), lds,
                      la.stream, la.iq, la.S, la.A, la.T, la.CP, la.U, la.B, la.tw, H, xhat, bits);
   return hipGetLastError();
 }
 
-// Accumulator tiers: the smallest tier holding ceil(U/64) subcarriers per lane.
+// Register-window tiers: the smallest instantiated QH >= ceil((U/2 + 1) / L).
 template <int N, bool ZF>
 hipError_t demod_n(const LaunchArgs& la, const float2* H, float2* xhat, uint8_t* bits) {
-  const int need = (la.U + 63) / 64;
-  constexpr int cap = (N - 2 + 63) / 64;
-  if (need <= 1) return demod_ni<N, 1, ZF>(la, H, xhat, bits);
-  if (need <= 2) return demod_ni<N, (cap < 2 ? cap : 2), ZF>(la, H, xhat, bits);
-  if constexpr (cap >= 4) {
-    if (need <= 4) return demod_ni<N, 4, ZF>(la, H, xhat, bits);
-  }
-  if constexpr (cap >= 8) {
-    if (need <= 8) return demod_ni<N, 8, ZF>(la, H, xhat, bits);
-  }
-  if constexpr (cap >= 16) {
-    if (need <= 10) return demod_ni<N, 10, ZF>(la, H, xhat, bits);
-    if (need <= 16) return demod_ni<N, 16, ZF>(la, H, xhat, bits);
-  }
-  if constexpr (cap >= 32) {
-    if (need <= 19) return demod_ni<N, 19, ZF>(la, H, xhat, bits);
-    if (need <= 24) return demod_ni<N, 24, ZF>(la, H, xhat, bits);
-    if (need <= 32) return demod_ni<N, 32, ZF>(la, H, xhat, bits);
+  constexpr int P = FftShape<N>::P, L = FftShape<N>::L;
+  const int need = (la.U / 2 + 1 + L - 1) / L;
+  if constexpr (P == 16) {
+    if (need <= 2) return demod_qh<N, 2, ZF>(la, H, xhat, bits);
+    if (need <= 4) return demod_qh<N, 4, ZF>(la, H, xhat, bits);
+    if (need <= 5) return demod_qh<N, 5, ZF>(la, H, xhat, bits);
+    if (need <= 8) return demod_qh<N, 8, ZF>(la, H, xhat, bits);
+  } else {
+    if (need <= 4) return demod_qh<N, 4, ZF>(la, H, xhat, bits);
+    if (need <= 8) return demod_qh<N, 8, ZF>(la, H, xhat, bits);
+    if (need <= 10) return demod_qh<N, 10, ZF>(la, H, xhat, bits);
+    if (need <= 16) return demod_qh<N, 16, ZF>(la, H, xhat, bits);
   }
   return hipErrorInvalidValue;
 }

@@ -107,6 +107,9 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-quality", action="store_true", help="skip the 20 dB quality figures")
+    ap.add_argument("--gen-unique", type=int, default=0,
+                    help="generate only this many distinct slots in this process and tile them over the "
+                         "workload (for profiler runs, where no worker processes may be started)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy (reference for the traffic counters)")
     ap.add_argument("--write-traffic", nargs=4, metavar=("DEMOD_FETCH", "DEMOD_WRITE", "COPY_FETCH", "COPY_WRITE"),
@@ -130,7 +133,14 @@ def main():
 
     # Generate every input before the process touches the GPU (fork-based pool).
     t0 = time.time()
-    fr = make_frames(cfg, workers=workers)
+    if args.gen_unique > 0:
+        import dataclasses
+        import numpy as np
+        k = min(args.gen_unique, S)
+        fr = make_frames(cfg, n_slots=k)
+        fr = dataclasses.replace(fr, iq=np.ascontiguousarray(fr.iq[np.arange(S) % k]))
+    else:
+        fr = make_frames(cfg, workers=workers)
     log(f"generated {cfg.name}: {fr.iq.nbytes / 1e6:.1f} MB int16 in {time.time() - t0:.1f} s")
     q20 = None
     if not args.no_quality:

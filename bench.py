@@ -99,12 +99,71 @@ def write_traffic(demod_fetch, demod_write, copy_fetch, copy_write):
     print(json.dumps(rec))
 
 
+BATCH_SEED = 190107499 + 3
+
+
+def bench_batch(args):
+    """Mixed batch: frames with antennas in {16,32,64,128}, FFT length in
+    {128..2048} (CP = N/14), QPSK/16-QAM/64-QAM, 1 pilot + 13 data symbols;
+    one graph launch per step after autotuning; per-frame latency percentiles."""
+    import numpy as np
+    from rxgen import make_batch
+    t0 = time.time()
+    bt = make_batch(args.frames, BATCH_SEED, workers=min(16, os.cpu_count() or 1))
+    log(f"generated batch of {args.frames} frames: {bt.iq.nbytes / 1e6:.1f} MB in {time.time() - t0:.1f} s")
+    import torch
+    from paper_1901_07499_amd import rx
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    batch = rx.Batch(bt.configs, [f.pilot for f in bt.frames])
+    iq = torch.from_numpy(bt.iq).to(dev)
+    out = batch.outputs(dev, want_H=False)
+    t0 = time.time()
+    batch.autotune(iq, out, reps=2)
+    classes = sorted({c.fft_len for c in bt.configs})
+    chosen = {n: batch.config(n) for n in classes}
+    log(f"autotuned in {time.time() - t0:.1f} s: {chosen}")
+    for _ in range(args.warmup):
+        batch.process(iq, out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        batch.process(iq, out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    samples = sum(c.n_sym * c.n_ant * (c.fft_len + c.cp_len) for c in bt.configs)
+    lat = []
+    for _ in range(max(5, min(args.steps, 20))):
+        batch.process(iq, out)
+        lat.append(batch.frame_latency_ms())
+    lat = np.concatenate(lat)
+    alg = sum(c.n_sym * c.n_ant * c.fft_len * 4 + (c.n_sym - 1) * c.n_used * (8 + c.bits_per_sym / 8)
+              for c in bt.configs)
+    rec = {"metric": "antenna-samples/s through FFT+LS+demod, batched mixed sizes in one graph launch",
+           "value": samples / (ms * 1e-3), "unit": "antenna-samples/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"batch_{args.frames}_mixed", "frames": args.frames,
+                      "antennas": [16, 32, 64, 128], "fft_len": [128, 256, 512, 1024, 2048],
+                      "input_MB": round(bt.iq.nbytes / 1e6, 1), "combiner": "mrc"},
+           "algorithmic_GBps": round(alg / (ms * 1e-3) / 1e9, 1),
+           "hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "frame_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                                "max": float(lat.max()), "samples": int(lat.size)},
+           "autotuned": {str(n): {"demod_waves": w, "est_jobs": j} for n, (w, j) in chosen.items()},
+           "kernel_hash": kernel_hash()}
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4", "batch"])
+    ap.add_argument("--frames", type=int, default=256, help="frames of the batch workload")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-quality", action="store_true", help="skip the 20 dB quality figures")
     ap.add_argument("--gen-unique", type=int, default=0,
@@ -126,6 +185,9 @@ def main():
               "so multi-GPU throughput is N x the one-GPU figure; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "batch":
+        bench_batch(args)
+        return
     from rxgen import C1, C2, C2_20DB, C4, make_frames
     cfg = {"c1": C1, "c2": C2, "c4": C4}[args.workload]
     S = cfg.n_slots

@@ -129,6 +129,59 @@ int rx_process_frame(rx_plan_t plan, const int16_t* iq, int64_t n_slots, float* 
  * Y float [S][T][A][N][2] in natural bin order.  For validating the FFT stage. */
 int rx_debug_fft(rx_plan_t plan, const int16_t* iq, int64_t n_slots, float* Y, void* hip_stream);
 
+/* ---------------------------------------------------------------------------
+ * Batches of frames with mixed shapes.  A frame is one slot (n_sym symbols,
+ * symbol 0 the pilot) with its own rx_params (antennas, FFT length, CP, used
+ * subcarriers, QAM order, pilot; combiner must be RX_COMB_MRC).  Frames are
+ * packed back to back in batch order: frame i's int16 samples start at
+ * iq_off[i] (int16 elements, layout [T][A][CP+N][2]), its estimate at
+ * h_off[i] complex entries of the H buffer ([A][U]), its x-hat at x_off[i]
+ * complex entries ([T-1][U]) and its bits at b_off[i] bytes ([T-1][U*b/8]).
+ * The path per frame is the one of rx_process_frame (paper Sec. II-B and
+ * II-C); the batch runs it for every frame in one graph launch.  Frames with
+ * equal FFT length share one persistent estimate kernel and one persistent
+ * demod kernel that take tiles from device work queues in frame order;
+ * different FFT lengths run on independent graph branches.
+ * ------------------------------------------------------------------------- */
+typedef struct rx_batch_s* rx_batch_t;
+
+/* Create a batch of n_frames (1..65536) frames on the current HIP device.
+ * Every frame is validated as by rx_params_check; pilots are copied. */
+int rx_batch_create(const rx_params* frames, int32_t n_frames, rx_batch_t* out);
+
+/* NULL-safe. */
+int rx_batch_destroy(rx_batch_t batch);
+
+/* Packed offsets: each non-NULL array receives n_frames + 1 entries, the last
+ * one being the total size (units as described above). */
+int rx_batch_layout(rx_batch_t batch, int64_t* iq_off, int64_t* h_off, int64_t* x_off, int64_t* b_off);
+
+/* Bytes of scratch rx_batch_process needs for the estimates when H == NULL. */
+size_t rx_batch_workspace_bytes(rx_batch_t batch);
+
+/* Run the whole batch on hip_stream (asynchronous; one graph launch).  iq
+ * required (4-byte aligned); H optional (then `workspace` holds the
+ * estimates, >= rx_batch_workspace_bytes, 256-byte aligned); xhat and bits
+ * optional but not both NULL.  The graph is rebuilt when the pointers differ
+ * from the previous call's. */
+int rx_batch_process(rx_batch_t batch, const int16_t* iq, float* H, float* xhat, uint8_t* bits,
+                     void* workspace, void* hip_stream);
+
+/* Time every launch configuration of every FFT-length class on these buffers
+ * (reps timed runs each, after one warm-up) and keep the fastest.
+ * Synchronous; overwrites the outputs. */
+int rx_batch_autotune(rx_batch_t batch, const int16_t* iq, float* H, float* xhat, uint8_t* bits,
+                      void* workspace, int32_t reps, void* hip_stream);
+
+/* Configuration in use for the class of FFT length fft_len: wavefronts per
+ * demod workgroup and jobs per estimate wavefront. */
+int rx_batch_config(rx_batch_t batch, int32_t fft_len, int32_t* demod_waves, int32_t* est_jobs);
+
+/* Per-frame completion time of the most recent rx_batch_process, in ms after
+ * the batch started on the device (device clock); ms has n_frames entries.
+ * Waits for hip_stream. */
+int rx_batch_frame_latency(rx_batch_t batch, double* ms, void* hip_stream);
+
 /* Static description of a status code. */
 const char* rx_status_string(int status);
 

@@ -43,6 +43,10 @@
 #ifndef RX_DEMOD_ILP
 #define RX_DEMOD_ILP 1
 #endif
+// Jobs (transforms of F antennas) per estimate wavefront.
+#ifndef RX_EST_JOBS
+#define RX_EST_JOBS 4
+#endif
 // How many jobs ahead a demod wavefront requests its input samples (1 or 2).
 #ifndef RX_DEMOD_PREFETCH
 #define RX_DEMOD_PREFETCH 1
@@ -70,61 +74,108 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t n) {
 }
 
 // ------------------------------------------------------------------ estimate
-template <int N, int W>
-__global__ __launch_bounds__(64 * W) void estimate_kernel(const uint32_t* __restrict__ iq, int A, int T, int CP,
-                                                          int U, const float2* __restrict__ tw,
-                                                          const float2* __restrict__ pf, float2* __restrict__ H,
-                                                          int blocks_per_slot) {
+// LS estimate of one slot's antennas a_first, a_first + W*F, ... (J jobs of F
+// antennas per wavefront), the next job's samples requested before the
+// current transform.  slot_iq: the slot's samples [T][A][CP+N]; Hs: its
+// estimate [A][U].  No workgroup barrier inside.
+template <int N, int W, int J>
+__device__ __forceinline__ void estimate_tile(const uint32_t* __restrict__ slot_iq, int A, int CP, int U,
+                                              const float2* __restrict__ pf, float2* __restrict__ Hs,
+                                              int a_first, float2* lds, const FftTwiddles<N>& twr) {
   using Sh = FftShape<N>;
-  extern __shared__ float2 lds[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int f = lane / Sh::L, li = lane % Sh::L;
-  const int64_t s = blockIdx.x / blocks_per_slot;
-  const int blk = blockIdx.x % blocks_per_slot;
-  const int a0 = (blk * W + wave) * Sh::F;
-  __shared__ float2 twtab[FftTwiddles<N>::kLdsFloat2 > 0 ? FftTwiddles<N>::kLdsFloat2 : 1];
+  const int a_step = W * Sh::F;
+  if (a_first >= A) return;
+  // subcarrier of each spectrum register (clamped for the pilot-factor load;
+  // unused bins are never stored) and its pilot factor
+  int dq[Sh::P];
+  float2 pq[Sh::P];
+#pragma unroll
+  for (int q = 0; q < Sh::P; q++) {
+    dq[q] = sub_of_bin(li + Sh::L * q, N, U);
+    pq[q] = pf[dq[q] >= 0 ? dq[q] : 0];
+  }
+  const uint32_t* pilot_sym = slot_iq + CP;  // symbol 0
+  auto rec_of = [&](int aj) {
+    const int a = aj + f;
+    return pilot_sym + (int64_t)(a < A ? a : aj) * (N + CP);
+  };
+  float2* buf = lds + (wave * Sh::F + f) * Lds<N>::kSlot;
+  uint32_t nxt[Sh::P];
+  load_symbol<N>(nxt, rec_of(a_first), li, a_first + f < A);
+#pragma unroll 1
+  for (int j = 0; j < J; j++) {
+    const int a0 = a_first + j * a_step;
+    if (a0 >= A) break;
+    float2 v[Sh::P];
+    unpack_symbol<N>(v, nxt);
+    const int an = a0 + a_step;
+    if (j + 1 < J && an < A) load_symbol<N>(nxt, rec_of(an), li, an + f < A);
+    fft_in_regs<N>(v, buf, li, twr);
+    const int a = a0 + f;
+    if (a < A) {
+      float2* hrow = Hs + (int64_t)a * U;
+#pragma unroll
+      for (int q = 0; q < Sh::P; q++)
+        if (dq[q] >= 0) hrow[dq[q]] = cmul(v[Spectrum<N>::reg(q)], pq[q]);
+    }
+    wave_fence();  // this job's LDS reads precede the next job's writes
+  }
+}
+
+// Fill the last-pass twiddle table (once per workgroup) and load this lane's
+// twiddles.  Contains a workgroup barrier when the table is used.
+template <int N>
+__device__ __forceinline__ void tile_setup(FftTwiddles<N>& twr, float2* twtab, const float2* __restrict__ tw) {
   if constexpr (FftTwiddles<N>::kLdsLast) {
     FftTwiddles<N>::P3Lds::fill(twtab, tw, threadIdx.x, blockDim.x);
     __syncthreads();
   }
-  if (a0 >= A) return;  // no workgroup barrier below
-  const int a = a0 + f;
-  const bool valid = a < A;
-  const uint32_t* rec = iq + ((s * T) * A + (valid ? a : a0)) * (int64_t)(N + CP) + CP;
-  uint32_t raw[Sh::P];
-  load_symbol<N>(raw, rec, li, valid);
+  twr.load(tw, (threadIdx.x & 63) % FftShape<N>::L, twtab);
+}
+
+// Uniform slots: workgroup = (slot, group of W*F*J antennas).
+template <int N, int W, int J>
+__global__ __launch_bounds__(64 * W) void estimate_kernel(const uint32_t* __restrict__ iq, int A, int T, int CP,
+                                                          int U, const float2* __restrict__ tw,
+                                                          const float2* __restrict__ pf, float2* __restrict__ H,
+                                                          int blocks_per_slot) {
+  extern __shared__ float2 lds[];
+  __shared__ float2 twtab[FftTwiddles<N>::kLdsFloat2 > 0 ? FftTwiddles<N>::kLdsFloat2 : 1];
   FftTwiddles<N> twr;
-  twr.load(tw, li, twtab);
-  float2 v[Sh::P];
-  unpack_symbol<N>(v, raw);
-  fft_in_regs<N>(v, lds + (wave * Sh::F + f) * Lds<N>::kSlot, li, twr);
-  if (valid) {
-    float2* hrow = H + (s * A + a) * (int64_t)U;
-#pragma unroll
-    for (int q = 0; q < Sh::P; q++) {
-      const int d = sub_of_bin(li + Sh::L * q, N, U);
-      if (d >= 0) hrow[d] = cmul(v[Spectrum<N>::reg(q)], pf[d]);
-    }
-  }
+  tile_setup<N>(twr, twtab, tw);
+  const int64_t s = blockIdx.x / blocks_per_slot;
+  const int blk = blockIdx.x % blocks_per_slot;
+  const int a_first = blk * (W * FftShape<N>::F * J) + (threadIdx.x >> 6) * FftShape<N>::F;
+  estimate_tile<N, W, J>(iq + s * T * (int64_t)A * (N + CP), A, CP, U, pf, H + s * A * (int64_t)U, a_first, lds,
+                         twr);
 }
 
 // ------------------------------------------------------------------ demod
+// One slot as seen by the per-tile routines (pointers already offset to the
+// slot; outputs may be null).
+struct SlotView {
+  const uint32_t* iq;  // samples, [T][A][CP+N] dwords
+  const float2* H;     // channel estimate, [A][U]
+  float2* xhat;        // [T-1][U]
+  uint8_t* bits;       // [T-1][U*B/8]
+  int A, T, CP, U, B;
+};
+
+// Demodulate data symbol t of one slot with the W wavefronts of the
+// workgroup.  Uses the dynamic LDS `lds` (exchange buffers, then the
+// reduction rows); every thread of the workgroup must call it.
 template <int N, int QH, int W, bool ZF>
-__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(RX_DEMOD_MIN_WAVES_PER_EU)))
-void demod_kernel(const uint32_t* __restrict__ iq, int64_t S, int A, int T, int CP, int U, int B,
-                  const float2* __restrict__ tw, const float2* __restrict__ H, float2* __restrict__ xhat,
-                  uint8_t* __restrict__ bits) {
+__device__ __forceinline__ void demod_tile(const SlotView& sv, int t, float2* lds, const FftTwiddles<N>& twr) {
   using Sh = FftShape<N>;
   constexpr int NI = 2 * QH;  // spectrum registers that can hold a used subcarrier
   static_assert(NI <= Sh::P, "window wider than the lane's spectrum");
-  extern __shared__ float2 lds[];
-  const int Td = T - 1;
-  const int64_t item = xcd_remap(blockIdx.x, S * Td);
-  const int64_t s = item / Td;
-  const int t = 1 + (int)(item % Td);
+  const int A = sv.A, T = sv.T, CP = sv.CP, U = sv.U, B = sv.B;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int f = lane / Sh::L, li = lane % Sh::L;
-  const float2* Hs = H + s * A * (int64_t)U;
+  const float2* Hs = sv.H;
+  const uint32_t* iq = sv.iq;
 
   // Window register i holds spectrum register q(i) = i (i < QH, bins
   // li + L*i above DC) or P - NI + i (bins below N, i.e. negative
@@ -167,14 +218,7 @@ void demod_kernel(const uint32_t* __restrict__ iq, int64_t S, int A, int T, int 
 #pragma unroll
   for (int c = 0; c < C; c++) bufs[c] = lds + ((wave * C + c) * Sh::F + f) * Lds<N>::kSlot;
   float2* const(&buf)[C] = bufs;
-  const int64_t sym_base = ((s * T + t) * A) * (int64_t)(N + CP) + CP;
-  __shared__ float2 twtab[FftTwiddles<N>::kLdsFloat2 > 0 ? FftTwiddles<N>::kLdsFloat2 : 1];
-  if constexpr (FftTwiddles<N>::kLdsLast) {
-    FftTwiddles<N>::P3Lds::fill(twtab, tw, threadIdx.x, blockDim.x);
-    __syncthreads();
-  }
-  FftTwiddles<N> twr;
-  twr.load(tw, li, twtab);
+  const int64_t sym_base = ((int64_t)t * A) * (N + CP) + CP;
   // Software pipeline over this wavefront's antennas: each job's samples are
   // requested D jobs ahead.
   constexpr int JA = Sh::F * C;  // antennas per job
@@ -264,7 +308,9 @@ void demod_kernel(const uint32_t* __restrict__ iq, int64_t S, int A, int T, int 
   __syncthreads();
 
   const int row_bytes = U * B / 8;
-  const int64_t out_row = s * Td + (t - 1);
+  const int64_t out_row = t - 1;
+  float2* xhat = sv.xhat;
+  uint8_t* bits = sv.bits;
   const float c16 = 3.16227766016837933f;  // sqrt(10)
   const float c64 = 6.48074069840786023f;  // sqrt(42)
   for (int qd = threadIdx.x; 4 * qd < U; qd += 64 * W) {
@@ -309,6 +355,106 @@ void demod_kernel(const uint32_t* __restrict__ iq, int64_t S, int A, int T, int 
       for (int byte = 0; byte < nbits / 8; byte++) o[byte] = (uint8_t)(acc >> (nbits - 8 * (byte + 1)));
     }
   }
+}
+
+
+// Uniform slots: one workgroup per (slot, data symbol).
+template <int N, int QH, int W, bool ZF>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(RX_DEMOD_MIN_WAVES_PER_EU)))
+void demod_kernel(const uint32_t* __restrict__ iq, int64_t S, int A, int T, int CP, int U, int B,
+                  const float2* __restrict__ tw, const float2* __restrict__ H, float2* __restrict__ xhat,
+                  uint8_t* __restrict__ bits) {
+  extern __shared__ float2 lds[];
+  __shared__ float2 twtab[FftTwiddles<N>::kLdsFloat2 > 0 ? FftTwiddles<N>::kLdsFloat2 : 1];
+  FftTwiddles<N> twr;
+  tile_setup<N>(twr, twtab, tw);
+  const int Td = T - 1;
+  const int64_t item = xcd_remap(blockIdx.x, S * Td);
+  const int64_t s = item / Td;
+  const int t = 1 + (int)(item % Td);
+  SlotView sv;
+  sv.iq = iq + s * T * (int64_t)A * (N + CP);
+  sv.H = H + s * A * (int64_t)U;
+  sv.xhat = xhat ? xhat + s * Td * (int64_t)U : nullptr;
+  sv.bits = bits ? bits + s * Td * (int64_t)(U * B / 8) : nullptr;
+  sv.A = A; sv.T = T; sv.CP = CP; sv.U = U; sv.B = B;
+  demod_tile<N, QH, W, ZF>(sv, t, lds, twr);
+}
+
+// ------------------------------------------------------------------ batches
+// Persistent kernels for a batch of frames sharing one FFT length: each
+// workgroup repeatedly takes the next tile from a device work queue (tiles
+// are numbered in frame order) and looks its frame up in a tile->frame map.
+__device__ __forceinline__ int next_tile(int* queue, int n_tiles, const int* tile_frame, int* tile_sh,
+                                         int* frame_sh, int& frame) {
+  if (threadIdx.x == 0) {
+    const int tile = atomicAdd(queue, 1);
+    *tile_sh = tile;
+    *frame_sh = tile < n_tiles ? tile_frame[tile] : -1;
+  }
+  __syncthreads();
+  const int tile = *tile_sh;
+  frame = *frame_sh;
+  __syncthreads();  // every thread has read both before thread 0 writes the next ones
+  return tile;
+}
+
+template <int N, int W, int J>
+__global__ __launch_bounds__(64 * W) void batch_estimate_kernel(const FrameDesc* __restrict__ fd,
+                                                                const int* __restrict__ tile_frame, int n_tiles,
+                                                                BatchIo io, const float2* __restrict__ tw,
+                                                                int* queue) {
+  extern __shared__ float2 lds[];
+  __shared__ float2 twtab[FftTwiddles<N>::kLdsFloat2 > 0 ? FftTwiddles<N>::kLdsFloat2 : 1];
+  __shared__ int tile_sh, frame_sh;
+  FftTwiddles<N> twr;
+  tile_setup<N>(twr, twtab, tw);
+  for (;;) {
+    int frame;
+    const int tile = next_tile(queue, n_tiles, tile_frame, &tile_sh, &frame_sh, frame);
+    if (tile >= n_tiles) break;
+    const FrameDesc d = fd[frame];
+    const int a_first = (tile - d.est_tile0) * (W * FftShape<N>::F * J) + (threadIdx.x >> 6) * FftShape<N>::F;
+    estimate_tile<N, W, J>(io.iq + d.iq_off, d.A, d.CP, d.U, d.pf, io.H + d.h_off, a_first, lds, twr);
+  }
+}
+
+template <int N, int QH, int W>
+__global__ __launch_bounds__(64 * W) void batch_demod_kernel(const FrameDesc* __restrict__ fd,
+                                                             const int* __restrict__ tile_frame, int n_tiles,
+                                                             BatchIo io, const float2* __restrict__ tw,
+                                                             int* queue, int* done_count,
+                                                             unsigned long long* done_time) {
+  extern __shared__ float2 lds[];
+  __shared__ float2 twtab[FftTwiddles<N>::kLdsFloat2 > 0 ? FftTwiddles<N>::kLdsFloat2 : 1];
+  __shared__ int tile_sh, frame_sh;
+  FftTwiddles<N> twr;
+  tile_setup<N>(twr, twtab, tw);
+  for (;;) {
+    int frame;
+    const int tile = next_tile(queue, n_tiles, tile_frame, &tile_sh, &frame_sh, frame);
+    if (tile >= n_tiles) break;
+    const FrameDesc d = fd[frame];
+    SlotView sv;
+    sv.iq = io.iq + d.iq_off;
+    sv.H = io.H + d.h_off;
+    sv.xhat = io.xhat ? io.xhat + d.x_off : nullptr;
+    sv.bits = io.bits ? io.bits + d.b_off : nullptr;
+    sv.A = d.A; sv.T = d.T; sv.CP = d.CP; sv.U = d.U; sv.B = d.B;
+    demod_tile<N, QH, W, false>(sv, 1 + tile - d.dem_tile0, lds, twr);
+    __syncthreads();  // outputs written and LDS free before the next tile
+    if (threadIdx.x == 0 && atomicAdd(done_count + d.index, 1) == d.T - 2)
+      done_time[d.index] = __builtin_amdgcn_s_memrealtime();  // last data symbol of the frame
+  }
+}
+
+// Start of a batch: clear the work queues and completion counters, stamp the
+// start time (100 MHz device clock).
+__global__ void batch_reset_kernel(int* queues, int n_queues, int* done_count, int n_frames,
+                                   unsigned long long* start_time) {
+  for (int i = threadIdx.x; i < n_queues; i += blockDim.x) queues[i] = 0;
+  for (int i = threadIdx.x; i < n_frames; i += blockDim.x) done_count[i] = 0;
+  if (threadIdx.x == 0) *start_time = __builtin_amdgcn_s_memrealtime();
 }
 
 // ------------------------------------------------------------------ g
@@ -364,6 +510,7 @@ __global__ __launch_bounds__(64 * W) void fft_kernel(const uint32_t* __restrict_
 // ------------------------------------------------------------------ launchers
 namespace {
 constexpr int kWavesEst = 4;
+constexpr int kJobsEst = RX_EST_JOBS;  // jobs per estimate wavefront
 constexpr int kWavesDemod = RX_DEMOD_WAVES;
 constexpr int kWavesFft = 4;
 
@@ -383,13 +530,14 @@ hipError_t allow_lds(K kernel, size_t bytes) {
 template <int N>
 hipError_t estimate_n(const LaunchArgs& la, float2* H) {
   using Sh = FftShape<N>;
-  const int jobs = (la.A + Sh::F - 1) / Sh::F;
-  const int bps = (jobs + kWavesEst - 1) / kWavesEst;
+  const int per_block = kWavesEst * Sh::F * kJobsEst;  // antennas per workgroup
+  const int bps = (la.A + per_block - 1) / per_block;
   const int64_t grid = la.S * bps;
   const size_t lds = fft_lds_bytes<N>(kWavesEst);
-  hipError_t e = allow_lds(estimate_kernel<N, kWavesEst>, lds);
+  hipError_t e = allow_lds(estimate_kernel<N, kWavesEst, kJobsEst>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((estimate_kernel<N, kWavesEst>), dim3((unsigned)grid), dim3(64 * kWavesEst), lds, la.stream, la.iq, la.A, la.T, la.CP, la.U, la.tw, la.pf, H, bps);
+  hipLaunchKernelGGL((estimate_kernel<N, kWavesEst, kJobsEst>), dim3((unsigned)grid), dim3(64 * kWavesEst), lds,
+                     la.stream, la.iq, la.A, la.T, la.CP, la.U, la.tw, la.pf, H, bps);
   return hipGetLastError();
 }
 
@@ -487,5 +635,72 @@ hipError_t launch_fft(const LaunchArgs& la, float2* Y) {
     default: return hipErrorInvalidValue;
   }
 }
+
+
+// ------------------------------------------------------------------ batch kernel lookup
+namespace {
+template <int N, int QH, int W>
+void demod_entry(BatchKernel& k) {
+  k.func = reinterpret_cast<const void*>(batch_demod_kernel<N, QH, W>);
+  k.block = 64 * W;
+}
+template <int N, int W, int J>
+void est_entry(BatchKernel& k) {
+  k.func = reinterpret_cast<const void*>(batch_estimate_kernel<N, W, J>);
+  k.block = 64 * W;
+}
+template <int N, int W>
+bool demod_qh_pick(int need, BatchKernel& k) {
+  if constexpr (FftShape<N>::P == 16) {
+    if (need <= 5) { demod_entry<N, 5, W>(k); return true; }
+    if (need <= 8) { demod_entry<N, 8, W>(k); return true; }
+  } else {
+    if (need <= 10) { demod_entry<N, 10, W>(k); return true; }
+    if (need <= 16) { demod_entry<N, 16, W>(k); return true; }
+  }
+  return false;
+}
+template <int N>
+bool batch_pick_n(int max_u, int demod_waves, int est_jobs, BatchKernel& dem, BatchKernel& est) {
+  constexpr int L = FftShape<N>::L, F = FftShape<N>::F;
+  const int need = (max_u / 2 + 1 + L - 1) / L;
+  bool ok = false;
+  switch (demod_waves) {
+    case 2: ok = demod_qh_pick<N, 2>(need, dem); break;
+    case 4: ok = demod_qh_pick<N, 4>(need, dem); break;
+    case 8: ok = demod_qh_pick<N, 8>(need, dem); break;
+    default: return false;
+  }
+  if (!ok) return false;
+  // LDS of the demod tile: exchange buffers, or the reduction rows if larger
+  dem.lds_fft = (size_t)demod_waves * F * Lds<N>::kSlot * sizeof(float2);
+  dem.lds_per_u = (size_t)demod_waves * F * (sizeof(float2) + sizeof(float));
+  switch (est_jobs) {
+    case 2: est_entry<N, 4, 2>(est); break;
+    case 4: est_entry<N, 4, 4>(est); break;
+    case 8: est_entry<N, 4, 8>(est); break;
+    default: return false;
+  }
+  est.lds_fft = (size_t)4 * F * Lds<N>::kSlot * sizeof(float2);
+  est.lds_per_u = 0;
+  est.ants_per_tile = 4 * F * est_jobs;
+  dem.ants_per_tile = 0;
+  return true;
+}
+}  // namespace
+
+bool batch_kernels(int N, int max_u, int demod_waves, int est_jobs, BatchKernel& dem, BatchKernel& est) {
+  switch (N) {
+    case 64: return batch_pick_n<64>(max_u, demod_waves, est_jobs, dem, est);
+    case 128: return batch_pick_n<128>(max_u, demod_waves, est_jobs, dem, est);
+    case 256: return batch_pick_n<256>(max_u, demod_waves, est_jobs, dem, est);
+    case 512: return batch_pick_n<512>(max_u, demod_waves, est_jobs, dem, est);
+    case 1024: return batch_pick_n<1024>(max_u, demod_waves, est_jobs, dem, est);
+    case 2048: return batch_pick_n<2048>(max_u, demod_waves, est_jobs, dem, est);
+    default: return false;
+  }
+}
+
+const void* batch_reset_func() { return reinterpret_cast<const void*>(batch_reset_kernel); }
 
 }  // namespace rx

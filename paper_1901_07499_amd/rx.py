@@ -22,7 +22,9 @@ RX_COMB_MRC, RX_COMB_ZF = 0, 1
 
 # Every symbol the header declares; the CPU test checks they are all exported.
 EXPORTS = ("rx_params_check", "rx_plan_create", "rx_plan_destroy", "rx_workspace_bytes", "rx_estimate",
-           "rx_demod", "rx_process_frame", "rx_debug_fft", "rx_status_string")
+           "rx_demod", "rx_process_frame", "rx_debug_fft", "rx_status_string",
+           "rx_batch_create", "rx_batch_destroy", "rx_batch_layout", "rx_batch_workspace_bytes",
+           "rx_batch_process", "rx_batch_autotune", "rx_batch_config", "rx_batch_frame_latency")
 
 
 class RxError(RuntimeError):
@@ -62,8 +64,18 @@ def _load() -> ctypes.CDLL:
     lib.rx_debug_fft.argtypes = [vp, vp, i64, vp, vp]
     lib.rx_status_string.argtypes = [ctypes.c_int]
     lib.rx_status_string.restype = ctypes.c_char_p
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    lib.rx_batch_create.argtypes = [ctypes.POINTER(rx_params), ctypes.c_int32, ctypes.POINTER(vp)]
+    lib.rx_batch_destroy.argtypes = [vp]
+    lib.rx_batch_layout.argtypes = [vp, i64p, i64p, i64p, i64p]
+    lib.rx_batch_workspace_bytes.argtypes = [vp]
+    lib.rx_batch_workspace_bytes.restype = sz
+    lib.rx_batch_process.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.rx_batch_autotune.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_int32, vp]
+    lib.rx_batch_config.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    lib.rx_batch_frame_latency.argtypes = [vp, ctypes.POINTER(ctypes.c_double), vp]
     for name in EXPORTS:
-        if name not in ("rx_workspace_bytes", "rx_status_string"):
+        if name not in ("rx_workspace_bytes", "rx_status_string", "rx_batch_workspace_bytes"):
             getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -108,6 +120,40 @@ def rx_debug_fft(plan, iq, n_slots, Y, stream) -> int:
 
 def rx_status_string(status: int) -> str:
     return _lib.rx_status_string(status).decode()
+
+
+def rx_batch_create(params_array, n_frames: int) -> Tuple[int, Optional[int]]:
+    out = ctypes.c_void_p()
+    st = _lib.rx_batch_create(params_array, n_frames, ctypes.byref(out))
+    return st, (out.value if st == RX_OK else None)
+
+
+def rx_batch_destroy(batch) -> int:
+    return _lib.rx_batch_destroy(batch)
+
+
+def rx_batch_layout(batch, iq_off, h_off, x_off, b_off) -> int:
+    return _lib.rx_batch_layout(batch, iq_off, h_off, x_off, b_off)
+
+
+def rx_batch_workspace_bytes(batch) -> int:
+    return _lib.rx_batch_workspace_bytes(batch)
+
+
+def rx_batch_process(batch, iq, H, xhat, bits, workspace, stream) -> int:
+    return _lib.rx_batch_process(batch, iq, H, xhat, bits, workspace, stream)
+
+
+def rx_batch_autotune(batch, iq, H, xhat, bits, workspace, reps, stream) -> int:
+    return _lib.rx_batch_autotune(batch, iq, H, xhat, bits, workspace, reps, stream)
+
+
+def rx_batch_config(batch, fft_len, demod_waves, est_jobs) -> int:
+    return _lib.rx_batch_config(batch, fft_len, demod_waves, est_jobs)
+
+
+def rx_batch_frame_latency(batch, ms, stream) -> int:
+    return _lib.rx_batch_frame_latency(batch, ms, stream)
 
 
 def make_params(n_ant: int, fft_len: int, cp_len: int, n_used: int, n_sym: int, bits_per_sym: int,
@@ -231,3 +277,87 @@ class Plan:
         if st != RX_OK:
             raise RxError(st, "rx_debug_fft")
         return Y
+
+
+class Batch:
+    """A batch of frames with mixed shapes (one slot each), processed by one graph launch.
+
+    ``frames``: sequence of (n_ant, fft_len, cp_len, n_used, n_sym, bits_per_sym, pilot)
+    tuples or objects with those attributes plus a pilot passed separately via
+    ``pilots``.  Buffers are flat and packed in batch order; ``layout`` gives the offsets.
+    """
+
+    def __init__(self, configs, pilots):
+        self.n = len(configs)
+        arr = (rx_params * self.n)()
+        self._keep = []
+        for i, (c, pil) in enumerate(zip(configs, pilots)):
+            p, buf = make_params(c.n_ant, c.fft_len, c.cp_len, c.n_used, c.n_sym, c.bits_per_sym, pil)
+            arr[i] = p
+            self._keep.append(buf)
+        st, self._b = rx_batch_create(arr, self.n)
+        if st != RX_OK:
+            raise RxError(st, "rx_batch_create")
+        offs = [(ctypes.c_int64 * (self.n + 1))() for _ in range(4)]
+        st = rx_batch_layout(self._b, *offs)
+        if st != RX_OK:
+            raise RxError(st, "rx_batch_layout")
+        self.iq_off, self.h_off, self.x_off, self.b_off = (np.array(o[:], dtype=np.int64) for o in offs)
+
+    def close(self):
+        if getattr(self, "_b", None):
+            rx_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def outputs(self, device, want_H=True):
+        import torch
+        H = torch.empty((int(self.h_off[-1]), 2), dtype=torch.float32, device=device) if want_H else None
+        x = torch.empty((int(self.x_off[-1]), 2), dtype=torch.float32, device=device)
+        b = torch.empty((int(self.b_off[-1]),), dtype=torch.uint8, device=device)
+        ws = None if want_H else torch.empty((max(1, rx_batch_workspace_bytes(self._b)),), dtype=torch.uint8,
+                                             device=device)
+        return H, x, b, ws
+
+    def _check(self, iq):
+        import torch
+        if iq.dtype != torch.int16 or iq.numel() != int(self.iq_off[-1]) or not iq.is_contiguous() or not iq.is_cuda:
+            raise ValueError(f"iq must be a contiguous int16 CUDA tensor of {int(self.iq_off[-1])} elements")
+
+    def process(self, iq, out):
+        import torch
+        self._check(iq)
+        H, x, b, ws = out
+        st = rx_batch_process(self._b, iq.data_ptr(), _ptr(H), _ptr(x), _ptr(b), _ptr(ws),
+                              torch.cuda.current_stream().cuda_stream)
+        if st != RX_OK:
+            raise RxError(st, "rx_batch_process")
+
+    def autotune(self, iq, out, reps: int = 3):
+        import torch
+        self._check(iq)
+        H, x, b, ws = out
+        st = rx_batch_autotune(self._b, iq.data_ptr(), _ptr(H), _ptr(x), _ptr(b), _ptr(ws), reps,
+                               torch.cuda.current_stream().cuda_stream)
+        if st != RX_OK:
+            raise RxError(st, "rx_batch_autotune")
+
+    def config(self, fft_len: int):
+        w, j = ctypes.c_int32(), ctypes.c_int32()
+        st = rx_batch_config(self._b, fft_len, ctypes.byref(w), ctypes.byref(j))
+        if st != RX_OK:
+            raise RxError(st, "rx_batch_config")
+        return w.value, j.value
+
+    def frame_latency_ms(self):
+        import torch
+        ms = (ctypes.c_double * self.n)()
+        st = rx_batch_frame_latency(self._b, ms, torch.cuda.current_stream().cuda_stream)
+        if st != RX_OK:
+            raise RxError(st, "rx_batch_frame_latency")
+        return np.array(ms[:])

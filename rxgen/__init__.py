@@ -3,8 +3,10 @@
 Holds the transmit side and the channel only (see ``rxgen.frames``); none of
 the receiver's arithmetic lives here.
 """
-from .frames import (C1, C2, C2_20DB, C4, CONFIGS, FrameConfig, Frames, make_frames,
-                     qam_symbols, tap_delays_powers, used_subcarrier_bins)
+from .frames import (C1, C2, C2_20DB, C4, CONFIGS, USED_BY_FFT, Batch, FrameConfig, Frames,
+                     batch_frame_config, make_batch, make_frames, qam_symbols, tap_delays_powers,
+                     used_subcarrier_bins)
 
-__all__ = ["C1", "C2", "C2_20DB", "C4", "CONFIGS", "FrameConfig", "Frames", "make_frames",
-           "qam_symbols", "tap_delays_powers", "used_subcarrier_bins"]
+__all__ = ["C1", "C2", "C2_20DB", "C4", "CONFIGS", "USED_BY_FFT", "Batch", "FrameConfig", "Frames",
+           "batch_frame_config", "make_batch", "make_frames", "qam_symbols", "tap_delays_powers",
+           "used_subcarrier_bins"]

@@ -273,3 +273,51 @@ def make_frames(cfg: FrameConfig, n_slots: Optional[int] = None, seed: Optional[
             if keep_float:
                 yk[s] = y
     return Frames(cfg, iq, pilot, bits, X, H, snr, scl, yk)
+
+
+# ---------------------------------------------------------------------------
+# Batches of frames with mixed shapes: one slot per frame; antennas from
+# {16, 32, 64, 128}, FFT length from {128, ..., 2048} with CP = round(N/14)
+# and the used-subcarrier count of that length, QPSK/16-QAM/64-QAM, sample
+# rate 15 kHz x N, 1 pilot + 13 data symbols.
+USED_BY_FFT = {64: 52, 128: 72, 256: 180, 512: 300, 1024: 600, 2048: 1200}
+
+
+def batch_frame_config(seed: int, index: int, antennas=(16, 32, 64, 128),
+                       fft_lens=(128, 256, 512, 1024, 2048), bits=(2, 4, 6)) -> FrameConfig:
+    """Shape of frame ``index`` of a mixed batch, drawn from its own seed stream."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, index, 7])))
+    N = int(rng.choice(fft_lens))
+    return FrameConfig(f"batch{seed}_f{index}", n_ant=int(rng.choice(antennas)), fft_len=N,
+                       cp_len=int(round(N / 14)), n_sym=14, n_used=USED_BY_FFT[N],
+                       bits_per_sym=int(rng.choice(bits)), n_slots=1, n_taps=10, tau_max_us=(0.5, 3.0),
+                       fs_hz=15e3 * N, snr_db=(5.0, 30.0), seed=seed * 1000 + index)
+
+
+def _batch_job(job):
+    cfg = job
+    return make_frames(cfg, n_slots=1)
+
+
+@dataclasses.dataclass
+class Batch:
+    """A packed batch: frames[i] is the Frames of frame i (one slot), iq the
+    concatenation of their int16 samples in batch order."""
+    frames: list
+    iq: np.ndarray  # int16, flat
+
+    @property
+    def configs(self):
+        return [f.cfg for f in self.frames]
+
+
+def make_batch(n_frames: int, seed: int, workers: int = 1, **shape_choices) -> Batch:
+    cfgs = [batch_frame_config(seed, i, **shape_choices) for i in range(n_frames)]
+    if workers > 1 and n_frames > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(min(workers, n_frames)) as pool:
+            frames = list(pool.imap(_batch_job, cfgs, chunksize=1))
+    else:
+        frames = [_batch_job(c) for c in cfgs]
+    iq = np.concatenate([f.iq.reshape(-1) for f in frames])
+    return Batch(frames, iq)

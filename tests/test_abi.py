@@ -117,3 +117,21 @@ def test_single_hip_runtime_in_process():
         if "libamdhip64" in line:
             paths.add(line.split()[-1])
     assert len(paths) == 1, paths
+
+
+def test_batch_create_validates_before_touching_the_gpu():
+    arr = (rx.rx_params * 2)()
+    p0, k0 = _p()
+    p1, k1 = _p(bits_per_sym=3)
+    arr[0], arr[1] = p0, p1
+    st, b = rx.rx_batch_create(arr, 2)
+    assert st == rx.RX_E_UNSUPPORTED and b is None
+    p2, k2 = _p(combiner=rx.RX_COMB_ZF)
+    arr[1] = p2
+    st, b = rx.rx_batch_create(arr, 2)
+    assert st == rx.RX_E_UNSUPPORTED                 # batches combine by MRC only
+    st, b = rx.rx_batch_create(arr, 0)
+    assert st == rx.RX_E_INVALID_ARG
+    assert rx.rx_batch_destroy(None) == rx.RX_OK
+    assert rx.rx_batch_workspace_bytes(None) == 0
+    assert rx.rx_batch_process(None, 16, 16, 16, 16, None, None) == rx.RX_E_INVALID_ARG

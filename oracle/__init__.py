@@ -38,7 +38,15 @@ def build(force: bool = True) -> str:
 class _Params(ctypes.Structure):
     _fields_ = [("n_ant", ctypes.c_int32), ("fft_len", ctypes.c_int32), ("cp_len", ctypes.c_int32),
                 ("n_used", ctypes.c_int32), ("n_sym", ctypes.c_int32), ("bits_per_sym", ctypes.c_int32),
-                ("combiner", ctypes.c_int32), ("pilot", ctypes.POINTER(ctypes.c_double))]
+                ("combiner", ctypes.c_int32), ("pilot", ctypes.POINTER(ctypes.c_double)),
+                ("pilot_spacing", ctypes.c_int32)]
+
+
+class _GenParams(ctypes.Structure):
+    _fields_ = [("fft_len", ctypes.c_int32), ("n_used", ctypes.c_int32), ("cp_len", ctypes.c_int32),
+                ("pilot_spacing", ctypes.c_int32), ("taps_min", ctypes.c_int32), ("taps_max", ctypes.c_int32),
+                ("tau_min", ctypes.c_int32), ("tau_max", ctypes.c_int32), ("snr_min_db", ctypes.c_double),
+                ("snr_max_db", ctypes.c_double), ("tap_decay_db", ctypes.c_double)]
 
 
 _lib = None
@@ -58,6 +66,18 @@ def _load():
             f = getattr(lib, name)
             f.argtypes = [ctypes.POINTER(_Params), src, ctypes.c_int64, dp, dp, dp, u8p, ctypes.c_int]
             f.restype = ctypes.c_int
+        lib.oracle_demod_given_h.argtypes = [ctypes.POINTER(_Params), ctypes.POINTER(ctypes.c_int16),
+                                             ctypes.c_int64, dp, dp, dp, u8p, ctypes.c_int]
+        lib.oracle_demod_given_h.restype = ctypes.c_int
+        lib.oracle_comb_interp.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.c_int64]
+        lib.oracle_comb_interp.restype = None
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        lib.oracle_philox4x64.argtypes = [u64p, u64p, u64p]
+        lib.oracle_philox4x64.restype = None
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        lib.oracle_gen_channels.argtypes = [ctypes.POINTER(_GenParams), ctypes.c_uint64, ctypes.c_int64,
+                                            ctypes.c_int64, dp, dp, i32p, i32p, dp, dp]
+        lib.oracle_gen_channels.restype = ctypes.c_int
         lib.oracle_fft_symbols.argtypes = [ctypes.POINTER(_Params), ctypes.POINTER(ctypes.c_int16),
                                            ctypes.c_int64, dp]
         lib.oracle_fft_symbols.restype = ctypes.c_int
@@ -109,25 +129,41 @@ class Result:
         self.H, self.g, self.xhat, self.bits = H, g, xhat, bits
 
 
-def _params(n_ant, fft_len, cp_len, n_used, n_sym, bits_per_sym, combiner, pilot):
+def _params(n_ant, fft_len, cp_len, n_used, n_sym, bits_per_sym, combiner, pilot, pilot_spacing=1):
     pil = np.ascontiguousarray(np.asarray(pilot, dtype=np.complex128)).view(np.float64)
-    p = _Params(n_ant, fft_len, cp_len, n_used, n_sym, bits_per_sym, combiner, _ptr(pil, ctypes.c_double))
+    p = _Params(n_ant, fft_len, cp_len, n_used, n_sym, bits_per_sym, combiner, _ptr(pil, ctypes.c_double),
+                pilot_spacing)
     return p, pil
 
 
 def process_frame(iq: np.ndarray, pilot: np.ndarray, *, n_ant: int, fft_len: int, cp_len: int,
                   n_used: int, n_sym: int, bits_per_sym: int, combiner: int = MRC,
-                  n_threads: int = 1, f64: bool = False) -> Result:
+                  n_threads: int = 1, f64: bool = False, pilot_spacing: int = 1,
+                  H_in: Optional[np.ndarray] = None) -> Result:
     """Run the oracle on ``iq`` (int16 [S][T][A][CP+N][2]) or, with ``f64``, on complex
-    samples (complex128 [S][T][A][CP+N])."""
-    p, keep = _params(n_ant, fft_len, cp_len, n_used, n_sym, bits_per_sym, combiner, pilot)
+    samples (complex128 [S][T][A][CP+N]).  ``pilot_spacing`` s > 1 selects the comb
+    pilot with linear interpolation; ``H_in`` (complex [S][A][U]) replaces the LS
+    estimate altogether (int16 input only; the returned H is then ``H_in``)."""
+    p, keep = _params(n_ant, fft_len, cp_len, n_used, n_sym, bits_per_sym, combiner, pilot, pilot_spacing)
     S = iq.shape[0]
     H = np.empty((S, n_ant, n_used), dtype=np.complex128)
     g = np.empty((S, n_used), dtype=np.float64)
     xhat = np.empty((S, n_sym - 1, n_used), dtype=np.complex128)
     bits = np.empty((S, n_sym - 1, n_used * bits_per_sym // 8), dtype=np.uint8)
     lib = _load()
-    if f64:
+    if H_in is not None:
+        if f64:
+            raise ValueError("H_in takes int16 input")
+        hin = np.ascontiguousarray(H_in, dtype=np.complex128)
+        if hin.shape != H.shape:
+            raise ValueError(f"H_in must have shape {H.shape}")
+        src = np.ascontiguousarray(iq, dtype=np.int16)
+        r = lib.oracle_demod_given_h(ctypes.byref(p), _ptr(src, ctypes.c_int16), S,
+                                     _ptr(hin.view(np.float64), ctypes.c_double), _ptr(g, ctypes.c_double),
+                                     _ptr(xhat.view(np.float64), ctypes.c_double),
+                                     _ptr(bits, ctypes.c_uint8), n_threads)
+        H[...] = hin
+    elif f64:
         src = np.ascontiguousarray(iq, dtype=np.complex128)
         r = lib.oracle_process_frame_f64(ctypes.byref(p), _ptr(src.view(np.float64), ctypes.c_double), S,
                                          _ptr(H.view(np.float64), ctypes.c_double), _ptr(g, ctypes.c_double),
@@ -166,4 +202,59 @@ def run_config(frames, combiner: int = MRC, n_threads: int = 1, slots=None) -> R
     iq = frames.iq if slots is None else frames.iq[slots]
     return process_frame(iq, frames.pilot, n_ant=c.n_ant, fft_len=c.fft_len, cp_len=c.cp_len,
                          n_used=c.n_used, n_sym=c.n_sym, bits_per_sym=c.bits_per_sym,
-                         combiner=combiner, n_threads=n_threads)
+                         combiner=combiner, n_threads=n_threads, pilot_spacing=c.pilot_spacing)
+
+
+def comb_interp(H: np.ndarray, spacing: int) -> np.ndarray:
+    """Comb interpolation of complex rows [..., U] whose entries d % spacing == 0
+    hold pilot estimates (the others are ignored); returns a new array."""
+    h = np.ascontiguousarray(H, dtype=np.complex128).copy()
+    U = h.shape[-1]
+    _load().oracle_comb_interp(U, spacing, _ptr(h.view(np.float64), ctypes.c_double), h.size // U)
+    return h
+
+
+def philox4x64(ctr, key) -> np.ndarray:
+    """One Philox4x64-10 block: four uint64 words."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint64)
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    out = np.empty(4, dtype=np.uint64)
+    _load().oracle_philox4x64(_ptr(c, ctypes.c_uint64), _ptr(k, ctypes.c_uint64), _ptr(out, ctypes.c_uint64))
+    return out
+
+
+class GenParams:
+    """Training-channel recipe (delays in samples, SNR in dB)."""
+
+    def __init__(self, fft_len=2048, n_used=1200, cp_len=144, pilot_spacing=4, taps=(8, 24),
+                 tau_samples=(15, 154), snr_db=(0.0, 30.0), tap_decay_db=3.0):
+        self.fft_len, self.n_used, self.cp_len, self.pilot_spacing = fft_len, n_used, cp_len, pilot_spacing
+        self.taps, self.tau_samples, self.snr_db, self.tap_decay_db = taps, tau_samples, snr_db, tap_decay_db
+
+    def _c(self):
+        return _GenParams(self.fft_len, self.n_used, self.cp_len, self.pilot_spacing, self.taps[0], self.taps[1],
+                          self.tau_samples[0], self.tau_samples[1], self.snr_db[0], self.snr_db[1],
+                          self.tap_decay_db)
+
+
+def gen_channels(gp: GenParams, seed: int, first_row: int, rows: int, draws: bool = False):
+    """Training rows: (H_true, H_ls), complex128 [rows][U] each; with ``draws``
+    also a dict of the per-row draws (n_taps, delays [rows][64], taps complex
+    [rows][64], snr_db)."""
+    ht = np.empty((rows, gp.n_used), dtype=np.complex128)
+    hl = np.empty((rows, gp.n_used), dtype=np.complex128)
+    nt = np.empty(rows, dtype=np.int32)
+    dl = np.empty((rows, 64), dtype=np.int32)
+    tp = np.empty((rows, 64), dtype=np.complex128)
+    sn = np.empty(rows, dtype=np.float64)
+    c = gp._c()
+    r = _load().oracle_gen_channels(ctypes.byref(c), seed, first_row, rows,
+                                    _ptr(ht.view(np.float64), ctypes.c_double),
+                                    _ptr(hl.view(np.float64), ctypes.c_double),
+                                    _ptr(nt, ctypes.c_int32), _ptr(dl, ctypes.c_int32),
+                                    _ptr(tp.view(np.float64), ctypes.c_double), _ptr(sn, ctypes.c_double))
+    if r:
+        raise ValueError(f"oracle rejected the generator parameters (status {r})")
+    if draws:
+        return ht, hl, {"n_taps": nt, "delays": dl, "taps": tp, "snr_db": sn}
+    return ht, hl

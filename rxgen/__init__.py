@@ -3,10 +3,12 @@
 Holds the transmit side and the channel only (see ``rxgen.frames``); none of
 the receiver's arithmetic lives here.
 """
-from .frames import (C1, C2, C2_20DB, C4, CONFIGS, USED_BY_FFT, Batch, FrameConfig, Frames,
-                     batch_frame_config, make_batch, make_frames, qam_symbols, tap_delays_powers,
+from .frames import (C1, C2, C2_20DB, C4, C5, C5_20DB, CONFIGS, DENOISER_LAYERS, DENOISER_TAPS,
+                     USED_BY_FFT, Batch, FrameConfig, Frames, batch_frame_config, denoiser_param_count,
+                     init_denoiser_params, make_batch, make_frames, qam_symbols, tap_delays_powers,
                      used_subcarrier_bins)
 
-__all__ = ["C1", "C2", "C2_20DB", "C4", "CONFIGS", "USED_BY_FFT", "Batch", "FrameConfig", "Frames",
-           "batch_frame_config", "make_batch", "make_frames", "qam_symbols", "tap_delays_powers",
+__all__ = ["C1", "C2", "C2_20DB", "C4", "C5", "C5_20DB", "CONFIGS", "DENOISER_LAYERS", "DENOISER_TAPS",
+           "USED_BY_FFT", "Batch", "FrameConfig", "Frames", "batch_frame_config", "denoiser_param_count",
+           "init_denoiser_params", "make_batch", "make_frames", "qam_symbols", "tap_delays_powers",
            "used_subcarrier_bins"]

@@ -51,6 +51,8 @@ class FrameConfig:
     seed: int
     tap_decay_db: float = 3.0        # power drop per tap index
     unit_spaced_taps: bool = False   # taps at delays 0..L-1 samples (tiny workload)
+    pilot_spacing: int = 1           # 1: every used subcarrier of symbol 0 is a pilot; s > 1: only d % s == 0 (comb)
+    n_taps_range: Optional[Tuple[int, int]] = None  # if set, L is drawn per slot uniformly in [lo, hi]
 
     @property
     def slot_samples(self) -> int:
@@ -86,7 +88,17 @@ C4 = FrameConfig("c4_A128_N2048_S500", n_ant=128, fft_len=2048, cp_len=144, n_sy
                  bits_per_sym=6, n_slots=500, n_taps=10, tau_max_us=(0.5, 3.0), fs_hz=30.72e6,
                  snr_db=(10.0, 30.0), seed=SEED_BASE + 4)
 
-CONFIGS = {c.name: c for c in (C1, C2, C2_20DB, C4)}
+# Learned-denoiser workload: the C4 shape with a comb pilot on every 4th used
+# subcarrier (300 of 1200; the pilot symbol carries nothing elsewhere), 8-24
+# taps per slot, maximum delay U[0.5, 5] us (clamped to the CP), SNR U[0, 30] dB.
+C5 = FrameConfig("c5_A128_N2048_comb4", n_ant=128, fft_len=2048, cp_len=144, n_sym=14, n_used=1200,
+                 bits_per_sym=6, n_slots=32, n_taps=24, tau_max_us=(0.5, 5.0), fs_hz=30.72e6,
+                 snr_db=(0.0, 30.0), seed=SEED_BASE + 5, pilot_spacing=4, n_taps_range=(8, 24))
+
+# The same at a fixed 20 dB (quality figures).
+C5_20DB = C5.replace(name="c5_A128_N2048_comb4_20dB", snr_db=(20.0, 20.0), seed=SEED_BASE + 15)
+
+CONFIGS = {c.name: c for c in (C1, C2, C2_20DB, C4, C5, C5_20DB)}
 
 
 def used_subcarrier_bins(fft_len: int, n_used: int) -> np.ndarray:
@@ -128,9 +140,10 @@ def qam_symbols(bits: np.ndarray, bits_per_sym: int) -> np.ndarray:
     return (re + 1j * im) * scale
 
 
-def tap_delays_powers(cfg: FrameConfig, tau_max_s: float) -> Tuple[np.ndarray, np.ndarray]:
+def tap_delays_powers(cfg: FrameConfig, tau_max_s: float, n_taps: Optional[int] = None
+                      ) -> Tuple[np.ndarray, np.ndarray]:
     """Delays (samples) and normalised powers of the L taps of one slot."""
-    L = cfg.n_taps
+    L = cfg.n_taps if n_taps is None else int(n_taps)
     if cfg.unit_spaced_taps or L == 1:
         delays = np.arange(L, dtype=np.int64)
     else:
@@ -175,8 +188,11 @@ def _slot(cfg: FrameConfig, rng: np.random.Generator, pilot: np.ndarray, bins: n
 
     lo, hi = cfg.tau_max_us
     tau = rng.uniform(lo, hi) * 1e-6
+    n_taps = None
+    if cfg.n_taps_range is not None:
+        n_taps = int(rng.integers(cfg.n_taps_range[0], cfg.n_taps_range[1] + 1))
     if channel == "rayleigh":
-        delays, p = tap_delays_powers(cfg, tau)
+        delays, p = tap_delays_powers(cfg, tau, n_taps)
         h = (rng.standard_normal((A, len(p))) + 1j * rng.standard_normal((A, len(p)))) * np.sqrt(p / 2.0)
     elif channel == "flat":
         delays = np.zeros(1, dtype=np.int64)
@@ -238,6 +254,8 @@ def make_frames(cfg: FrameConfig, n_slots: Optional[int] = None, seed: Optional[
     and the result does not depend on ``workers`` (processes used to generate
     slots in parallel; start them before the process touches a GPU).
     ``pilot`` replaces the seeded BPSK pilot by any U non-zero complex values.
+    With ``cfg.pilot_spacing`` s > 1 the pilot symbol is a comb: the seeded
+    BPSK values sit on subcarriers d % s == 0 and the others carry zero.
     """
     S = cfg.n_slots if n_slots is None else int(n_slots)
     seed = cfg.seed if seed is None else int(seed)
@@ -247,6 +265,8 @@ def make_frames(cfg: FrameConfig, n_slots: Optional[int] = None, seed: Optional[
     children = np.random.SeedSequence(seed).spawn(first_slot + S + 1)
     prng = np.random.Generator(np.random.PCG64(children[0]))
     seeded_pilot = (1 - 2 * prng.integers(0, 2, size=U)).astype(np.complex128)   # BPSK +-1
+    if cfg.pilot_spacing > 1:
+        seeded_pilot[np.arange(U) % cfg.pilot_spacing != 0] = 0.0
     pilot = seeded_pilot if pilot is None else np.asarray(pilot, dtype=np.complex128).reshape(U)
     bins = used_subcarrier_bins(N, U)
 
@@ -321,3 +341,30 @@ def make_batch(n_frames: int, seed: int, workers: int = 1, **shape_choices) -> B
         frames = [_batch_job(c) for c in cfgs]
     iq = np.concatenate([f.iq.reshape(-1) for f in frames])
     return Batch(frames, iq)
+
+
+# ---------------------------------------------------------------------------
+# Initial weights of the learned channel-estimate denoiser (random numbers
+# only; the network itself is defined by the receiver).  Layers 2->32->32->32->2
+# channels, 7 taps; per layer the weights W[co][ci][k] then the biases b[co].
+DENOISER_LAYERS = ((2, 32), (32, 32), (32, 32), (32, 2))
+DENOISER_TAPS = 7
+
+
+def denoiser_param_count() -> int:
+    return sum(co * ci * DENOISER_TAPS + co for ci, co in DENOISER_LAYERS)
+
+
+def init_denoiser_params(seed: int, last_scale: float = 0.1) -> np.ndarray:
+    """He-uniform weights (bound sqrt(6 / fan_in)), zero biases; the last
+    layer's weights are scaled by ``last_scale`` so an untrained network is
+    close to the identity on its residual path.  float32 [P]."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 1901])))
+    out = []
+    for li, (ci, co) in enumerate(DENOISER_LAYERS):
+        bound = math.sqrt(6.0 / (ci * DENOISER_TAPS))
+        w = rng.uniform(-bound, bound, size=(co, ci, DENOISER_TAPS))
+        if li == len(DENOISER_LAYERS) - 1:
+            w *= last_scale
+        out += [w.reshape(-1), np.zeros(co)]
+    return np.concatenate(out).astype(np.float32)

@@ -1,0 +1,179 @@
+"""Pins of the FP64 denoiser oracle (oracle/denoiser.py).
+
+The analytic gradient is checked against central finite differences of the
+loss in FP64; the convolution against numpy's correlate; the residual form,
+the row scale and Adam's first step against closed forms; the bfloat16
+rounding against torch's conversion and against its error bound.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import denoiser as dn
+from rxgen import denoiser_param_count, init_denoiser_params
+
+
+def _rows(R, U, seed, smooth=True):
+    rng = np.random.default_rng(seed)
+    h = rng.standard_normal((R, U)) + 1j * rng.standard_normal((R, U))
+    if smooth:
+        k = np.ones(9) / 9
+        h = np.stack([np.convolve(r, k, mode="same") for r in h])
+    return h
+
+
+def test_param_count_and_layout():
+    assert dn.param_count() == denoiser_param_count() == 15330
+    th = np.arange(dn.param_count(), dtype=np.float64)
+    layers = dn.unpack(th)
+    assert [W.shape for W, _ in layers] == [(32, 2, 7), (32, 32, 7), (32, 32, 7), (2, 32, 7)]
+    np.testing.assert_array_equal(dn.pack(layers), th)
+    assert layers[0][1][0] == 448 and layers[1][0][0, 0, 0] == 480
+
+
+def test_conv_matches_numpy_correlate():
+    rng = np.random.default_rng(1)
+    U = 37
+    x = rng.standard_normal((1, 1, U))
+    W = rng.standard_normal((1, 1, 7))
+    b = np.array([0.25])
+    want = np.correlate(x[0, 0], W[0, 0], mode="same") + 0.25
+    np.testing.assert_allclose(dn.conv(x, W, b)[0, 0], want, rtol=1e-13, atol=1e-13)
+
+
+def test_conv_sums_over_input_channels():
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal((2, 3, 20))
+    W = rng.standard_normal((4, 3, 7))
+    b = rng.standard_normal(4)
+    y = dn.conv(x, W, b)
+    for r in range(2):
+        for o in range(4):
+            want = b[o] + sum(np.correlate(x[r, c], W[o, c], mode="same") for c in range(3))
+            np.testing.assert_allclose(y[r, o], want, rtol=1e-12, atol=1e-12)
+
+
+def test_zero_last_layer_is_identity_and_loss_closed_form():
+    th = init_denoiser_params(3).astype(np.float64)
+    layers = dn.unpack(th)
+    layers[3][0][...] = 0.0
+    layers[3][1][...] = 0.0
+    th = dn.pack(layers)
+    h = _rows(3, 40, 4)
+    ht = _rows(3, 40, 5)
+    np.testing.assert_allclose(dn.forward(th, h), h, rtol=1e-15, atol=0)
+    s = np.sqrt(np.mean(np.abs(h) ** 2, axis=1))
+    want = np.mean(np.abs(h / s[:, None] - ht / s[:, None]) ** 2)
+    loss, _ = dn.loss_grad(th, h, ht)
+    assert abs(loss - want) < 1e-13 * want
+
+
+def test_last_layer_bias_shifts_output_by_row_scale():
+    th = init_denoiser_params(3).astype(np.float64)
+    layers = dn.unpack(th)
+    layers[3][0][...] = 0.0
+    layers[3][1][...] = (0.5, -0.25)
+    h = _rows(2, 16, 6)
+    s = np.sqrt(np.mean(np.abs(h) ** 2, axis=1))
+    np.testing.assert_allclose(dn.forward(dn.pack(layers), h), h + s[:, None] * (0.5 - 0.25j), rtol=1e-14)
+
+
+def test_scale_equivariance():
+    th = init_denoiser_params(7).astype(np.float64)
+    h = _rows(2, 30, 8)
+    for c in (0.5, 3.0, 1e3):
+        np.testing.assert_allclose(dn.forward(th, c * h), c * dn.forward(th, h), rtol=1e-12,
+                                   atol=1e-12 * c * np.abs(h).max())
+
+
+def test_zero_row_passes_through():
+    th = init_denoiser_params(7).astype(np.float64)
+    h = _rows(2, 30, 8)
+    h[1] = 0
+    out = dn.forward(th, h)
+    np.testing.assert_array_equal(out[1], 0)
+    loss, g = dn.loss_grad(th, h, _rows(2, 30, 9))
+    assert np.all(np.isfinite(g)) and np.isfinite(loss)
+
+
+def test_gradient_matches_central_differences():
+    rng = np.random.default_rng(11)
+    th = init_denoiser_params(11, last_scale=1.0).astype(np.float64)
+    th += 0.05 * rng.standard_normal(th.size)       # non-zero biases too
+    h = _rows(2, 24, 12)
+    ht = h + 0.3 * _rows(2, 24, 13)
+    loss, g = dn.loss_grad(th, h, ht)
+    idx = np.concatenate([rng.choice(th.size, 150, replace=False),
+                          [0, 447, 448, 479, 480, 15330 - 3, 15330 - 1]])   # layer edges, biases
+    eps = 1e-6
+    fd = np.empty(idx.size)
+    for n, i in enumerate(idx):
+        tp, tm = th.copy(), th.copy()
+        tp[i] += eps
+        tm[i] -= eps
+        fd[n] = (dn.loss_grad(tp, h, ht)[0] - dn.loss_grad(tm, h, ht)[0]) / (2 * eps)
+    scale = np.abs(g).max()
+    np.testing.assert_allclose(g[idx], fd, rtol=1e-5, atol=1e-7 * scale)
+
+
+def test_bf16_rounding_matches_torch():
+    rng = np.random.default_rng(3)
+    x = np.concatenate([rng.standard_normal(4000) * 10.0 ** rng.integers(-8, 8, 4000),
+                        [1 + 2 ** -8, 1 + 3 * 2 ** -8, -1 - 2 ** -8, 0.0, -0.0, 65504.0]])
+    want = torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(dn.bf16(x), want)
+    assert dn.bf16(np.array([1 + 2 ** -8]))[0] == 1.0               # tie to even
+    assert dn.bf16(np.array([1 + 3 * 2 ** -8]))[0] == 1 + 2 ** -6
+
+
+def test_bf16_operands_stay_within_their_error_bound():
+    # Each rounding is within 2^-9 relative; over 4 layers the refined part of
+    # the output must stay within a few percent of the exact one, and the
+    # gradient direction must be essentially unchanged.
+    th = init_denoiser_params(21, last_scale=1.0).astype(np.float64)
+    h = _rows(4, 64, 22)
+    ht = h + 0.2 * _rows(4, 64, 23)
+    exact = dn.forward(th, h) - h
+    rounded = dn.forward(th, h, bf16_ops=True) - h
+    rel = np.linalg.norm(rounded - exact) / np.linalg.norm(exact)
+    assert 1e-5 < rel < 2e-2
+    _, g0 = dn.loss_grad(th, h, ht)
+    _, g1 = dn.loss_grad(th, h, ht, bf16_ops=True)
+    assert np.linalg.norm(g1 - g0) / np.linalg.norm(g0) < 3e-2
+
+
+def test_adam_first_step_closed_form():
+    rng = np.random.default_rng(4)
+    th = rng.standard_normal(50)
+    g = rng.standard_normal(50)
+    lr, eps = 1e-3, 1e-8
+    new, m, v = dn.adam(th, np.zeros(50), np.zeros(50), g, 1, lr, eps=eps)
+    # bias correction makes m_hat = g and v_hat = g^2 on step 1
+    np.testing.assert_allclose(new, th - lr * g / (np.abs(g) + eps), rtol=1e-12)
+    np.testing.assert_allclose(m, 0.1 * g, rtol=1e-15)
+    np.testing.assert_allclose(v, 0.001 * g * g, rtol=1e-12)
+
+
+def test_adam_constant_gradient_moves_lr_per_step():
+    th = np.zeros(3)
+    m = v = np.zeros(3)
+    g = np.array([2.0, -0.5, 1e-3])
+    for t in range(1, 6):
+        th, m, v = dn.adam(th, m, v, g, t, 0.01, eps=0.0)
+    # with a constant gradient m_hat = g and v_hat = g^2 exactly at every step
+    np.testing.assert_allclose(th, -0.05 * np.sign(g), rtol=1e-12)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_training_reduces_loss(seed):
+    # A few Adam steps on a fixed batch must lower the loss (plain gradient descent sanity).
+    th = init_denoiser_params(seed).astype(np.float64)
+    h_true = _rows(4, 48, 100 + seed)
+    h = h_true + 0.3 * _rows(4, 48, 200 + seed, smooth=False)
+    m = v = np.zeros_like(th)
+    first = None
+    for t in range(1, 16):
+        loss, g = dn.loss_grad(th, h, h_true)
+        first = loss if first is None else first
+        th, m, v = dn.adam(th, m, v, g, t, 3e-3)
+    assert dn.loss_grad(th, h, h_true)[0] < 0.8 * first

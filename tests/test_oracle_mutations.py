@@ -42,6 +42,102 @@ MUTANTS = {
 }
 
 
+# Mistakes in the comb estimate and the training-channel generator; their pins
+# live in their own suites.
+COMB_GEN_MUTANTS = {
+    "comb_interp_by_index": ("(double)(signed_freq(d, U) - signed_freq(d0, U)) /\n"
+                             "                       (double)(signed_freq(d1, U) - signed_freq(d0, U));",
+                             "(double)(d - d0) / (double)(d1 - d0);"),
+    "comb_holds_first_pilot": ("h[2 * d] = h[2 * last];", "h[2 * d] = h[0];"),
+    "comb_interp_wrong_end": ("h[2 * d] = h[2 * d0] + t * (h[2 * d1] - h[2 * d0]);",
+                              "h[2 * d] = h[2 * d1] + t * (h[2 * d1] - h[2 * d0]);"),
+    "philox_nine_rounds": ("for (int round = 0; round < 10; round++)", "for (int round = 0; round < 9; round++)"),
+    "philox_no_key_bump": ("k0 += 0x9E3779B97F4A7C15ull;", "k0 += 0;"),
+    "gen_delay_truncated": ("(l * span + (L - 1) / 2) / (L - 1)", "(l * span) / (L - 1)"),
+    "gen_phase_sign": ("+ I * sin(-2.0 * ORACLE_PI * m / N)", "+ I * sin(2.0 * ORACLE_PI * m / N)"),
+    "gen_power_not_normalised": ("/ psum / 2.0) * z;", "/ 2.0) * z;"),
+    "gen_noise_too_strong": ("sqrt(pow(10.0, -snr_db / 10.0) / 2.0)", "sqrt(pow(10.0, -snr_db / 10.0))"),
+    "gen_noise_block_shared": ("block_words(seed, row, noise_block + j / 2, b);",
+                               "block_words(seed, row, 1 + j / 2, b);"),
+    "gen_wrong_uniform": ("(double)(2 * (w >> 41) + 1) * 0x1p-24", "(double)((w >> 40) + 1) * 0x1p-24"),
+}
+
+
+def _compile_mutant(tmp_path, old, new, name):
+    src = open(SRC).read()
+    assert src.count(old) >= 1, f"mutation anchor for {name} not found"
+    mutated = tmp_path / "rx_oracle_mut.c"
+    mutated.write_text(src.replace(old, new, 1))
+    lib = tmp_path / "liboracle_mut.so"
+    subprocess.check_call(["gcc", "-std=c11", "-O1", "-fPIC", "-shared", "-ffp-contract=off",
+                           "-o", str(lib), str(mutated), "-lm", "-lpthread"])
+    return lib
+
+
+@pytest.mark.parametrize("name", sorted(COMB_GEN_MUTANTS))
+def test_comb_and_generator_pins_catch_planted_mistake(name, tmp_path):
+    old, new = COMB_GEN_MUTANTS[name]
+    lib = _compile_mutant(tmp_path, old, new, name)
+    env = dict(os.environ, RX_ORACLE_LIB=str(lib))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_comb.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_gen.py")],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"
+
+
+# Mistakes in the FP64 denoiser (numpy); the pins are the functions of
+# test_oracle_denoiser run against the mutated module.
+DN_SRC = os.path.join(ROOT, "oracle", "denoiser.py")
+DN_MUTANTS = {
+    "transposed_conv_index": ("dp[:, :, 2 * HALF - k:2 * HALF - k + U]", "dp[:, :, k:k + U]"),
+    "relu_mask_dropped": ("delta = rnd(gx * (xin > 0))", "delta = rnd(gx)"),
+    "bias_grad_missing_rows": ("gb = delta.sum(axis=(0, 2))", "gb = delta[0].sum(axis=1)"),
+    "loss_not_normalised": ("n = R * U", "n = U"),
+    "conv_flipped_taps": ("W[:, :, k], xp[:, :, k:k + U])\n    return y",
+                          "W[:, :, TAPS - 1 - k], xp[:, :, k:k + U])\n    return y"),
+    "no_relu_forward": ("x = rnd(np.maximum(a, 0.0))", "x = rnd(a)"),
+    "residual_missing": ("out = h + s[:, None] * (a4[:, 0] + 1j * a4[:, 1])",
+                         "out = s[:, None] * (a4[:, 0] + 1j * a4[:, 1])"),
+    "scale_is_mean_abs": ("np.sqrt(np.mean(np.abs(h) ** 2, axis=-1))", "np.mean(np.abs(h), axis=-1)"),
+    "adam_no_bias_correction": ("mh = m / (1 - beta1 ** step)", "mh = m"),
+    "adam_sqrt_missing": ("(np.sqrt(vh) + eps)", "(vh + eps)"),
+    "bf16_truncates": ("(u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000", "u & 0xFFFF0000"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(DN_MUTANTS))
+def test_denoiser_pins_catch_planted_mistake(name, tmp_path):
+    import importlib.util
+
+    from tests import test_oracle_denoiser as suite
+    old, new = DN_MUTANTS[name]
+    src = open(DN_SRC).read()
+    assert src.count(old) >= 1, f"mutation anchor for {name} not found"
+    path = tmp_path / "denoiser_mut.py"
+    path.write_text(src.replace(old, new, 1))
+    spec = importlib.util.spec_from_file_location("denoiser_mut", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    saved = suite.dn
+    suite.dn = mod
+    failed = []
+    try:
+        for fname in sorted(dir(suite)):
+            fn = getattr(suite, fname)
+            if not fname.startswith("test_") or not callable(fn):
+                continue
+            args = [0] if fname == "test_training_reduces_loss" else []
+            try:
+                fn(*args)
+            except Exception as e:  # a pin failed (or the mutant crashed)
+                failed.append((fname, type(e).__name__))
+                break
+    finally:
+        suite.dn = saved
+    assert failed, f"mutant {name} survived the pins"
+
+
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_pins_catch_planted_mistake(name, tmp_path):
     old, new = MUTANTS[name]

@@ -86,7 +86,16 @@ typedef struct {
   int32_t combiner;     /* RX_COMB_MRC or RX_COMB_ZF */
   int32_t n_users;      /* K, must be 1 (single-user uplink) */
   const float* pilot;   /* HOST pointer to U complex pilot values in d order;
-                           every value non-zero and finite; copied by rx_plan_create */
+                           every pilot value non-zero and finite; copied by rx_plan_create */
+  int32_t pilot_spacing; /* 0 or 1: block pilot, every used subcarrier of symbol 0
+                            carries one (the paper's arrangement).  s > 1 (s <= U): comb
+                            pilot on d = 0, s, 2s, ... only (values elsewhere ignored);
+                            LS there, then every subcarrier is interpolated along a
+                            straight line in signed frequency between the pilot at or
+                            below it and the next pilot (spanning the DC gap), and past
+                            the last pilot that pilot's value is held.  The comb form is
+                            the standard LS-with-interpolation estimator the learned
+                            refinement below starts from.  Batches need 0 or 1. */
 } rx_params;
 
 /* Validate parameters without touching the GPU.  Returns RX_OK or the status
@@ -106,7 +115,8 @@ size_t rx_workspace_bytes(rx_plan_t plan, int64_t n_slots);
 
 /* Channel estimation (paper Sec. II-B, first symbol; Sec. II-C, LS):
  * CP removal + FFT of the pilot symbol of every antenna, then
- * H[s][a][d] = Y_0[s][a][k_d] * conj(X_p[d]) / |X_p[d]|^2.
+ * H[s][a][d] = Y_0[s][a][k_d] * conj(X_p[d]) / |X_p[d]|^2 (on the comb and
+ * interpolated in between when pilot_spacing > 1).
  * iq required; H required; g optional (NULL = not computed); workspace unused. */
 int rx_estimate(rx_plan_t plan, const int16_t* iq, int64_t n_slots, float* H, float* g,
                 void* workspace, void* hip_stream);
@@ -181,6 +191,93 @@ int rx_batch_config(rx_batch_t batch, int32_t fft_len, int32_t* demod_waves, int
  * the batch started on the device (device clock); ms has n_frames entries.
  * Waits for hip_stream. */
 int rx_batch_frame_latency(rx_batch_t batch, double* ms, void* hip_stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned refinement of a comb-pilot LS channel estimate.
+ *
+ * The paper estimates the channel by LS alone (Sec. II-C, LS paragraph); a
+ * comb pilot (rx_params.pilot_spacing) gives LS on every s-th subcarrier plus
+ * linear interpolation, and this network refines that estimate per antenna.
+ * For a row h[0..U) (one antenna of one slot; complex):
+ *   s = sqrt(mean_d |h[d]|^2),  x0 = (Re h / s, Im h / s)        2 channels
+ *   a_l[co][d] = b_l[co] + sum_ci sum_k W_l[co][ci][k] x_{l-1}[ci][d+k-3],
+ *     k = 0..6, x zero outside 0..U-1;  x_l = max(a_l, 0) for l = 1, 2, 3;
+ *     channels 2 -> 32 -> 32 -> 32 -> 2
+ *   out[d] = h[d] + s (a_4[0][d] + i a_4[1][d])      (a zero row passes through)
+ * Parameters (RX_DN_PARAMS floats): for l = 1..4, W_l[co][ci][k] then b_l[co].
+ * Training loss: mean over rows and d of |x0 + a_4 - h_true / s|^2, with the
+ * gradient by backpropagation and Adam (Kingma and Ba, 2015).  Products run
+ * on bf16 MFMA with FP32 accumulation: weights, activations and backward
+ * deltas are rounded to bf16 (nearest even) where they enter a product.
+ * Rows are float [rows][U][2]; every pointer is a device pointer.
+ * ------------------------------------------------------------------------- */
+#define RX_DN_PARAMS 15330
+
+typedef struct rx_dn_s* rx_dn_t;
+
+/* Create a denoiser for rows of n_used (2..2046) subcarriers on the current
+ * device.  Holds a copy of the parameters and their bf16 operand layout
+ * (about 130 KB).  Parameters must be loaded before use. */
+int rx_dn_create(int32_t n_used, rx_dn_t* out);
+
+/* NULL-safe. */
+int rx_dn_destroy(rx_dn_t dn);
+
+/* Load parameters (device float [RX_DN_PARAMS]) into the denoiser. */
+int rx_dn_load(rx_dn_t dn, const float* params, void* hip_stream);
+
+/* out = refined rows.  H_out may equal H_in (each row is read before it is
+ * written); otherwise the two must not overlap.  rows == 0 is a no-op. */
+int rx_dn_apply(rx_dn_t dn, const float* H_in, int64_t rows, float* H_out, void* hip_stream);
+
+/* Device scratch for rx_dn_grad and rx_dn_train_step on `rows` rows
+ * (activations and deltas in bf16, per-workgroup partial sums). */
+size_t rx_dn_workspace_bytes(rx_dn_t dn, int64_t rows);
+
+/* Loss (device float [1]) and its gradient (device float [RX_DN_PARAMS]) at
+ * the loaded parameters for inputs H_in and targets H_true (both
+ * [rows][U][2]).  workspace >= rx_dn_workspace_bytes, 256-byte aligned.
+ * Deterministic for a given row count.  grad and loss may be NULL. */
+int rx_dn_grad(rx_dn_t dn, const float* H_in, const float* H_true, int64_t rows, float* grad, float* loss,
+               void* workspace, void* hip_stream);
+
+/* One training step: gradient at the loaded parameters (which must equal
+ * params), then Adam step number `step` (>= 1) on params, m and v (device
+ * float [RX_DN_PARAMS] each; m, v start at zero) with learning rate lr,
+ * then the updated params are loaded.  loss may be NULL. */
+int rx_dn_train_step(rx_dn_t dn, float* params, float* adam_m, float* adam_v, int64_t step, float lr, float beta1,
+                     float beta2, float eps, const float* H_in, const float* H_true, int64_t rows, float* loss,
+                     void* workspace, void* hip_stream);
+
+/* Recipe of the training channels (delays in samples). */
+typedef struct {
+  int32_t fft_len;       /* N, power of two, 64..2048 */
+  int32_t n_used;        /* U, even, 2..N-2 */
+  int32_t cp_len;        /* delays are clamped to the CP, 0 <= CP < N */
+  int32_t pilot_spacing; /* comb spacing s, 1..U */
+  int32_t taps_min, taps_max;  /* 1 <= taps_min <= taps_max <= 64 */
+  int32_t tau_min, tau_max;    /* maximum excess delay range, samples, 0 <= min <= max */
+  float snr_min_db, snr_max_db;
+  float tap_decay_db;    /* power drop per tap */
+} rx_chan_gen;
+
+/* Training pairs for rows first_row .. first_row+rows-1 of a seeded stream
+ * (each row independent): the true frequency response H_true (unit mean
+ * power) and the comb LS estimate H_ls (true response plus complex Gaussian
+ * noise of variance 10^(-snr/10) on the pilots, then comb interpolation).
+ * Per row, from Philox4x64-10 (counter {block, row, 0, 0}, key {seed, 0};
+ * uniform u = (2 (w >> 41) + 1) 2^-24; integer draws ((w >> 32) n) >> 32;
+ * complex normals by Box-Muller):
+ *   block 0: L = taps_min + int(w0, taps_max-taps_min+1), span = tau_min +
+ *     int(w1, tau_max-tau_min+1), snr = snr_min + (snr_max-snr_min) u(w2);
+ *   delay_l = (l span + (L-1)/2) / (L-1) clamped to the CP; power of tap l
+ *     proportional to 10^(-decay l / 10), summing to 1; gain of tap l from
+ *     block 1 + l/2 (words 0,1 for even l, 2,3 for odd);
+ *   H_true[d] = sum_l h_l exp(-2 pi i (f_d delay_l mod N) / N);
+ *   pilot j's noise from block 1 + ceil(taps_max/2) + j/2.
+ * H_true or H_ls may be NULL. */
+int rx_dn_generate(const rx_chan_gen* gen, uint64_t seed, int64_t first_row, int64_t rows, float* H_true,
+                   float* H_ls, void* hip_stream);
 
 /* Static description of a status code. */
 const char* rx_status_string(int status);

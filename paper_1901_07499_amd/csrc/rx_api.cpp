@@ -28,6 +28,8 @@ namespace {
 
 bool is_pow2(int32_t n) { return n > 0 && (n & (n - 1)) == 0; }
 
+int spacing(const rx_params& p) { return p.pilot_spacing > 1 ? p.pilot_spacing : 1; }
+
 bool aligned(const void* p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
 
 int check_params(const rx_params* p) {
@@ -45,7 +47,8 @@ int check_params(const rx_params* p) {
   if ((p->n_used * p->bits_per_sym) % 8) return RX_E_INVALID_ARG;
   if (p->combiner != RX_COMB_MRC && p->combiner != RX_COMB_ZF) return RX_E_UNSUPPORTED;
   if (!p->pilot) return RX_E_INVALID_ARG;
-  for (int d = 0; d < p->n_used; d++) {
+  if (p->pilot_spacing < 0 || p->pilot_spacing > p->n_used) return RX_E_INVALID_ARG;
+  for (int d = 0; d < p->n_used; d += spacing(*p)) {
     const float re = p->pilot[2 * d], im = p->pilot[2 * d + 1];
     if (!std::isfinite(re) || !std::isfinite(im) || (re == 0.0f && im == 0.0f)) return RX_E_INVALID_ARG;
   }
@@ -87,6 +90,7 @@ rx::LaunchArgs launch_args(rx_plan_t plan, const int16_t* iq, int64_t S, void* s
   la.B = plan->p.bits_per_sym;
   la.tw = plan->tw;
   la.pf = plan->pf;
+  la.ps = spacing(plan->p);
   la.stream = reinterpret_cast<hipStream_t>(stream);
   return la;
 }
@@ -122,7 +126,8 @@ int rx_plan_create(const rx_params* p, rx_plan_t* out) {
   for (int d = 0; d < U; d++) {
     const double re = p->pilot[2 * d], im = p->pilot[2 * d + 1];
     const double m2 = re * re + im * im;
-    pf[d] = make_float2((float)(re / m2), (float)(-im / m2));
+    // subcarriers off a comb carry no pilot: their factor is never used
+    pf[d] = d % spacing(*p) ? make_float2(0.f, 0.f) : make_float2((float)(re / m2), (float)(-im / m2));
   }
   if (hipMalloc(&plan->tw, sizeof(float2) * N) != hipSuccess ||
       hipMalloc(&plan->pf, sizeof(float2) * U) != hipSuccess) {

@@ -3,7 +3,10 @@
 // estimate_kernel  pilot symbol of every (slot, antenna): int16 load with the
 //                  CP skipped, FFT, LS divide by the pilot (paper Sec. II-B;
 //                  Sec. II-C, LS paragraph), H written in subcarrier order
-//                  straight from the FFT's output registers.
+//                  straight from the FFT's output registers.  With a comb
+//                  pilot (every ps-th used subcarrier) the LS values go to
+//                  the transform's LDS slot and every subcarrier is then
+//                  interpolated from them (comb_value).
 // demod_kernel     one workgroup per (slot, data symbol): its wavefronts split
 //                  the antennas, FFT each antenna's symbol and accumulate the
 //                  MRC sums conj(H) Y and |H|^2 of the used subcarriers from
@@ -26,6 +29,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "rx_comb.hpp"
 #include "rx_fft.hpp"
 #include "rx_launch.h"
 
@@ -81,7 +85,7 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t n) {
 template <int N, int W, int J>
 __device__ __forceinline__ void estimate_tile(const uint32_t* __restrict__ slot_iq, int A, int CP, int U,
                                               const float2* __restrict__ pf, float2* __restrict__ Hs,
-                                              int a_first, float2* lds, const FftTwiddles<N>& twr) {
+                                              int a_first, float2* lds, const FftTwiddles<N>& twr, int ps) {
   using Sh = FftShape<N>;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int f = lane / Sh::L, li = lane % Sh::L;
@@ -114,11 +118,25 @@ __device__ __forceinline__ void estimate_tile(const uint32_t* __restrict__ slot_
     if (j + 1 < J && an < A) load_symbol<N>(nxt, rec_of(an), li, an + f < A);
     fft_in_regs<N>(v, buf, li, twr);
     const int a = a0 + f;
-    if (a < A) {
-      float2* hrow = Hs + (int64_t)a * U;
+    if (ps <= 1) {
+      if (a < A) {
+        float2* hrow = Hs + (int64_t)a * U;
+#pragma unroll
+        for (int q = 0; q < Sh::P; q++)
+          if (dq[q] >= 0) hrow[dq[q]] = cmul(v[Spectrum<N>::reg(q)], pq[q]);
+      }
+    } else {
+      // comb: LS on the pilot subcarriers into this transform's LDS slot
+      // (the FFT's last LDS reads are behind), then every subcarrier
+      wave_fence();
 #pragma unroll
       for (int q = 0; q < Sh::P; q++)
-        if (dq[q] >= 0) hrow[dq[q]] = cmul(v[Spectrum<N>::reg(q)], pq[q]);
+        if (dq[q] >= 0 && dq[q] % ps == 0) buf[dq[q] / ps] = cmul(v[Spectrum<N>::reg(q)], pq[q]);
+      wave_fence();
+      if (a < A) {
+        float2* hrow = Hs + (int64_t)a * U;
+        for (int d = li; d < U; d += Sh::L) hrow[d] = comb_value(buf, d, U, ps);
+      }
     }
     wave_fence();  // this job's LDS reads precede the next job's writes
   }
@@ -140,7 +158,7 @@ template <int N, int W, int J>
 __global__ __launch_bounds__(64 * W) void estimate_kernel(const uint32_t* __restrict__ iq, int A, int T, int CP,
                                                           int U, const float2* __restrict__ tw,
                                                           const float2* __restrict__ pf, float2* __restrict__ H,
-                                                          int blocks_per_slot) {
+                                                          int blocks_per_slot, int ps) {
   extern __shared__ float2 lds[];
   __shared__ float2 twtab[FftTwiddles<N>::kLdsFloat2 > 0 ? FftTwiddles<N>::kLdsFloat2 : 1];
   FftTwiddles<N> twr;
@@ -149,7 +167,7 @@ __global__ __launch_bounds__(64 * W) void estimate_kernel(const uint32_t* __rest
   const int blk = blockIdx.x % blocks_per_slot;
   const int a_first = blk * (W * FftShape<N>::F * J) + (threadIdx.x >> 6) * FftShape<N>::F;
   estimate_tile<N, W, J>(iq + s * T * (int64_t)A * (N + CP), A, CP, U, pf, H + s * A * (int64_t)U, a_first, lds,
-                         twr);
+                         twr, ps);
 }
 
 // ------------------------------------------------------------------ demod
@@ -415,7 +433,7 @@ __global__ __launch_bounds__(64 * W) void batch_estimate_kernel(const FrameDesc*
     if (tile >= n_tiles) break;
     const FrameDesc d = fd[frame];
     const int a_first = (tile - d.est_tile0) * (W * FftShape<N>::F * J) + (threadIdx.x >> 6) * FftShape<N>::F;
-    estimate_tile<N, W, J>(io.iq + d.iq_off, d.A, d.CP, d.U, d.pf, io.H + d.h_off, a_first, lds, twr);
+    estimate_tile<N, W, J>(io.iq + d.iq_off, d.A, d.CP, d.U, d.pf, io.H + d.h_off, a_first, lds, twr, 1);
   }
 }
 
@@ -537,7 +555,7 @@ hipError_t estimate_n(const LaunchArgs& la, float2* H) {
   hipError_t e = allow_lds(estimate_kernel<N, kWavesEst, kJobsEst>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((estimate_kernel<N, kWavesEst, kJobsEst>), dim3((unsigned)grid), dim3(64 * kWavesEst), lds,
-                     la.stream, la.iq, la.A, la.T, la.CP, la.U, la.tw, la.pf, H, bps);
+                     la.stream, la.iq, la.A, la.T, la.CP, la.U, la.tw, la.pf, H, bps, la.ps);
   return hipGetLastError();
 }
 

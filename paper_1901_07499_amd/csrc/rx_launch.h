@@ -12,7 +12,8 @@ struct LaunchArgs {
   int64_t S;
   int A, N, CP, U, T, B;
   const float2* tw;    // tw[k] = exp(-2 pi i k / N), k < N
-  const float2* pf;    // pf[d] = conj(Xp[d]) / |Xp[d]|^2
+  const float2* pf;    // pf[d] = conj(Xp[d]) / |Xp[d]|^2 (pilot subcarriers only)
+  int ps;              // pilot spacing: 1 = block pilot, > 1 = comb on d % ps == 0
   hipStream_t stream;
 };
 
@@ -56,5 +57,50 @@ struct BatchKernel {
 // {2,4,8} jobs per estimate wavefront.  False if unsupported.
 bool batch_kernels(int N, int max_u, int demod_waves, int est_jobs, BatchKernel& dem, BatchKernel& est);
 const void* batch_reset_func();
+
+// ---- learned refinement of the channel estimate (rx_denoise.hip)
+// Parameter vector: per layer W[co][ci][7] then b[co]; layers 2->32->32->32->2.
+constexpr int kParams = 15330;
+constexpr int kPW1 = 0, kPB1 = 448, kPW2 = 480, kPB2 = 7648, kPW3 = 7680, kPB3 = 14848, kPW4 = 14880,
+              kPB4 = 15328;
+// bf16 MFMA operand fragments of the weights, in 16-byte units (64 per block):
+// forward F1[2], F2[2][7], F3[2][7], F4[7]; transposed G4[2], G3[2][7], G2[2][7].
+constexpr int kF1 = 0, kF2 = 128, kF3 = 1024, kF4 = 1920, kG4 = 2368, kG3 = 2496, kG2 = 3392,
+              kFragUnits = 4288;
+
+// Training buffers (bf16 bits, channel-major [row][channel][UP], UP = U
+// rounded up to 8) and partial sums.
+struct DnTrainIo {
+  const float2* Htrue;
+  int64_t UP;
+  float inv_count;  // 1 / (rows * U)
+  uint16_t *X0, *X1, *X2, *X3;  // x0 (2 channels), x1..x3 (32)
+  uint16_t *D1, *D2, *D3, *D4;  // deltas: d1..d3 (32 channels), d4 (2)
+  float* part;       // [grid][kParams] weight-gradient partials
+  float* loss_part;  // [grid]
+};
+
+struct AdamArgs {
+  float* theta;  // null: no update
+  float* m;
+  float* v;
+  float lr, beta1, beta2, eps, c1, c2;  // c1 = 1/(1-beta1^t), c2 = 1/(1-beta2^t)
+};
+
+// Training-channel recipe (delays in samples).
+struct GenArgs {
+  int N, U, CP, ps, taps_min, taps_max, tau_min, tau_max;
+  float snr_min, snr_max, decay_db;
+};
+
+int dn_grid(int64_t rows);
+hipError_t dn_relayout(const float* theta, uint16_t* frag, hipStream_t st);
+hipError_t dn_apply(const float2* Hin, int64_t rows, int U, const void* frag, const float* theta, float2* Hout,
+                    hipStream_t st);
+hipError_t dn_train(const float2* Hin, const float2* Htrue, int64_t rows, int U, const void* frag,
+                    const float* theta, const DnTrainIo& io, float* grad, float* loss, const AdamArgs& adam,
+                    hipStream_t st);
+hipError_t dn_generate(const GenArgs& g, uint64_t seed, int64_t first_row, int64_t rows, float2* Htrue,
+                       float2* Hls, hipStream_t st);
 
 }  // namespace rx

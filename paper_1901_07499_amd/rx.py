@@ -24,7 +24,17 @@ RX_COMB_MRC, RX_COMB_ZF = 0, 1
 EXPORTS = ("rx_params_check", "rx_plan_create", "rx_plan_destroy", "rx_workspace_bytes", "rx_estimate",
            "rx_demod", "rx_process_frame", "rx_debug_fft", "rx_status_string",
            "rx_batch_create", "rx_batch_destroy", "rx_batch_layout", "rx_batch_workspace_bytes",
-           "rx_batch_process", "rx_batch_autotune", "rx_batch_config", "rx_batch_frame_latency")
+           "rx_batch_process", "rx_batch_autotune", "rx_batch_config", "rx_batch_frame_latency",
+           "rx_dn_create", "rx_dn_destroy", "rx_dn_load", "rx_dn_apply", "rx_dn_workspace_bytes", "rx_dn_grad",
+           "rx_dn_train_step", "rx_dn_generate")
+RX_DN_PARAMS = 15330
+
+
+class rx_chan_gen(ctypes.Structure):
+    _fields_ = [("fft_len", ctypes.c_int32), ("n_used", ctypes.c_int32), ("cp_len", ctypes.c_int32),
+                ("pilot_spacing", ctypes.c_int32), ("taps_min", ctypes.c_int32), ("taps_max", ctypes.c_int32),
+                ("tau_min", ctypes.c_int32), ("tau_max", ctypes.c_int32), ("snr_min_db", ctypes.c_float),
+                ("snr_max_db", ctypes.c_float), ("tap_decay_db", ctypes.c_float)]
 
 
 class RxError(RuntimeError):
@@ -37,7 +47,7 @@ class rx_params(ctypes.Structure):
     _fields_ = [("n_ant", ctypes.c_int32), ("fft_len", ctypes.c_int32), ("cp_len", ctypes.c_int32),
                 ("n_used", ctypes.c_int32), ("n_sym", ctypes.c_int32), ("bits_per_sym", ctypes.c_int32),
                 ("combiner", ctypes.c_int32), ("n_users", ctypes.c_int32),
-                ("pilot", ctypes.POINTER(ctypes.c_float))]
+                ("pilot", ctypes.POINTER(ctypes.c_float)), ("pilot_spacing", ctypes.c_int32)]
 
 
 def _load() -> ctypes.CDLL:
@@ -74,8 +84,19 @@ def _load() -> ctypes.CDLL:
     lib.rx_batch_autotune.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_int32, vp]
     lib.rx_batch_config.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     lib.rx_batch_frame_latency.argtypes = [vp, ctypes.POINTER(ctypes.c_double), vp]
+    f32 = ctypes.c_float
+    lib.rx_dn_create.argtypes = [ctypes.c_int32, ctypes.POINTER(vp)]
+    lib.rx_dn_destroy.argtypes = [vp]
+    lib.rx_dn_load.argtypes = [vp, vp, vp]
+    lib.rx_dn_apply.argtypes = [vp, vp, i64, vp, vp]
+    lib.rx_dn_workspace_bytes.argtypes = [vp, i64]
+    lib.rx_dn_workspace_bytes.restype = sz
+    lib.rx_dn_grad.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp]
+    lib.rx_dn_train_step.argtypes = [vp, vp, vp, vp, i64, f32, f32, f32, f32, vp, vp, i64, vp, vp, vp]
+    lib.rx_dn_generate.argtypes = [ctypes.POINTER(rx_chan_gen), ctypes.c_uint64, i64, i64, vp, vp, vp]
     for name in EXPORTS:
-        if name not in ("rx_workspace_bytes", "rx_status_string", "rx_batch_workspace_bytes"):
+        if name not in ("rx_workspace_bytes", "rx_status_string", "rx_batch_workspace_bytes",
+                        "rx_dn_workspace_bytes"):
             getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -156,12 +177,48 @@ def rx_batch_frame_latency(batch, ms, stream) -> int:
     return _lib.rx_batch_frame_latency(batch, ms, stream)
 
 
+def rx_dn_create(n_used: int) -> Tuple[int, Optional[int]]:
+    out = ctypes.c_void_p()
+    st = _lib.rx_dn_create(n_used, ctypes.byref(out))
+    return st, (out.value if st == RX_OK else None)
+
+
+def rx_dn_destroy(dn) -> int:
+    return _lib.rx_dn_destroy(dn)
+
+
+def rx_dn_load(dn, params, stream) -> int:
+    return _lib.rx_dn_load(dn, params, stream)
+
+
+def rx_dn_apply(dn, H_in, rows, H_out, stream) -> int:
+    return _lib.rx_dn_apply(dn, H_in, rows, H_out, stream)
+
+
+def rx_dn_workspace_bytes(dn, rows) -> int:
+    return _lib.rx_dn_workspace_bytes(dn, rows)
+
+
+def rx_dn_grad(dn, H_in, H_true, rows, grad, loss, workspace, stream) -> int:
+    return _lib.rx_dn_grad(dn, H_in, H_true, rows, grad, loss, workspace, stream)
+
+
+def rx_dn_train_step(dn, params, m, v, step, lr, beta1, beta2, eps, H_in, H_true, rows, loss, workspace,
+                     stream) -> int:
+    return _lib.rx_dn_train_step(dn, params, m, v, step, lr, beta1, beta2, eps, H_in, H_true, rows, loss,
+                                 workspace, stream)
+
+
+def rx_dn_generate(gen: rx_chan_gen, seed: int, first_row: int, rows: int, H_true, H_ls, stream) -> int:
+    return _lib.rx_dn_generate(ctypes.byref(gen), seed, first_row, rows, H_true, H_ls, stream)
+
+
 def make_params(n_ant: int, fft_len: int, cp_len: int, n_used: int, n_sym: int, bits_per_sym: int,
-                pilot: Sequence[complex], combiner: int = RX_COMB_MRC, n_users: int = 1):
+                pilot: Sequence[complex], combiner: int = RX_COMB_MRC, n_users: int = 1, pilot_spacing: int = 1):
     """Build an ``rx_params`` plus the float buffer its pilot pointer refers to (keep both alive)."""
     pil = np.ascontiguousarray(np.asarray(pilot, dtype=np.complex64)).view(np.float32)
     p = rx_params(n_ant, fft_len, cp_len, n_used, n_sym, bits_per_sym, combiner, n_users,
-                  pil.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+                  pil.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), pilot_spacing)
     return p, pil
 
 
@@ -179,18 +236,21 @@ class Plan:
     """
 
     def __init__(self, n_ant: int, fft_len: int, cp_len: int, n_used: int, n_sym: int, bits_per_sym: int,
-                 pilot: Sequence[complex], combiner: int = RX_COMB_MRC, n_users: int = 1):
+                 pilot: Sequence[complex], combiner: int = RX_COMB_MRC, n_users: int = 1,
+                 pilot_spacing: int = 1):
         self.n_ant, self.fft_len, self.cp_len, self.n_used = n_ant, fft_len, cp_len, n_used
         self.n_sym, self.bits_per_sym, self.combiner = n_sym, bits_per_sym, combiner
+        self.pilot_spacing = pilot_spacing
         self._params, self._pilot = make_params(n_ant, fft_len, cp_len, n_used, n_sym, bits_per_sym, pilot,
-                                                combiner, n_users)
+                                                combiner, n_users, pilot_spacing)
         st, self._plan = rx_plan_create(self._params)
         if st != RX_OK:
             raise RxError(st, "rx_plan_create")
 
     @classmethod
     def from_config(cls, cfg, pilot, combiner: int = RX_COMB_MRC) -> "Plan":
-        return cls(cfg.n_ant, cfg.fft_len, cfg.cp_len, cfg.n_used, cfg.n_sym, cfg.bits_per_sym, pilot, combiner)
+        return cls(cfg.n_ant, cfg.fft_len, cfg.cp_len, cfg.n_used, cfg.n_sym, cfg.bits_per_sym, pilot, combiner,
+                   pilot_spacing=getattr(cfg, "pilot_spacing", 1))
 
     def close(self):
         if getattr(self, "_plan", None):
@@ -361,3 +421,105 @@ class Batch:
         if st != RX_OK:
             raise RxError(st, "rx_batch_frame_latency")
         return np.array(ms[:])
+
+
+# ---------------------------------------------------------------- learned estimate refinement
+def chan_gen(fft_len=2048, n_used=1200, cp_len=144, pilot_spacing=4, taps=(8, 24), tau_samples=(15, 154),
+             snr_db=(0.0, 30.0), tap_decay_db=3.0) -> rx_chan_gen:
+    """Training-channel recipe (see ``rx_dn_generate`` in include/rx.h)."""
+    return rx_chan_gen(fft_len, n_used, cp_len, pilot_spacing, taps[0], taps[1], tau_samples[0], tau_samples[1],
+                       snr_db[0], snr_db[1], tap_decay_db)
+
+
+def generate(gen: rx_chan_gen, seed: int, first_row: int, rows: int, device, want_true=True, want_ls=True):
+    """(H_true, H_ls) float32 [rows][U][2] tensors on ``device`` (either may be None)."""
+    import torch
+    ht = torch.empty((rows, gen.n_used, 2), dtype=torch.float32, device=device) if want_true else None
+    hl = torch.empty((rows, gen.n_used, 2), dtype=torch.float32, device=device) if want_ls else None
+    st = rx_dn_generate(gen, seed, first_row, rows, _ptr(ht), _ptr(hl), torch.cuda.current_stream().cuda_stream)
+    if st != RX_OK:
+        raise RxError(st, "rx_dn_generate")
+    return ht, hl
+
+
+class Denoiser:
+    """The learned refinement of comb-pilot LS estimates for rows of ``n_used``
+    subcarriers (float32 [rows][U][2] CUDA tensors), on torch's current stream."""
+
+    def __init__(self, n_used: int):
+        self.n_used = n_used
+        st, self._dn = rx_dn_create(n_used)
+        if st != RX_OK:
+            raise RxError(st, "rx_dn_create")
+        self._ws = None
+
+    def close(self):
+        if getattr(self, "_dn", None):
+            rx_dn_destroy(self._dn)
+            self._dn = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _stream():
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+
+    def load(self, params):
+        self._check(params, (RX_DN_PARAMS,))
+        st = rx_dn_load(self._dn, params.data_ptr(), self._stream())
+        if st != RX_OK:
+            raise RxError(st, "rx_dn_load")
+
+    def _check(self, t, shape):
+        import torch
+        if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+            raise ValueError(f"expected a contiguous float32 CUDA tensor of shape {shape}")
+
+    def apply(self, H, out=None):
+        import torch
+        rows = H.shape[0]
+        self._check(H, (rows, self.n_used, 2))
+        out = torch.empty_like(H) if out is None else out
+        st = rx_dn_apply(self._dn, H.data_ptr(), rows, out.data_ptr(), self._stream())
+        if st != RX_OK:
+            raise RxError(st, "rx_dn_apply")
+        return out
+
+    def workspace(self, rows: int):
+        import torch
+        need = rx_dn_workspace_bytes(self._dn, rows)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty((need,), dtype=torch.uint8, device="cuda")
+        return self._ws
+
+    def grad(self, H, H_true):
+        import torch
+        rows = H.shape[0]
+        self._check(H, (rows, self.n_used, 2))
+        self._check(H_true, (rows, self.n_used, 2))
+        g = torch.empty((RX_DN_PARAMS,), dtype=torch.float32, device=H.device)
+        loss = torch.empty((1,), dtype=torch.float32, device=H.device)
+        ws = self.workspace(rows)
+        st = rx_dn_grad(self._dn, H.data_ptr(), H_true.data_ptr(), rows, g.data_ptr(), loss.data_ptr(),
+                        ws.data_ptr(), self._stream())
+        if st != RX_OK:
+            raise RxError(st, "rx_dn_grad")
+        return loss, g
+
+    def train_step(self, params, m, v, step: int, H, H_true, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+                   loss=None):
+        rows = H.shape[0]
+        for t in (params, m, v):
+            self._check(t, (RX_DN_PARAMS,))
+        self._check(H, (rows, self.n_used, 2))
+        self._check(H_true, (rows, self.n_used, 2))
+        ws = self.workspace(rows)
+        st = rx_dn_train_step(self._dn, params.data_ptr(), m.data_ptr(), v.data_ptr(), step, lr, beta1, beta2, eps,
+                              H.data_ptr(), H_true.data_ptr(), rows, _ptr(loss), ws.data_ptr(), self._stream())
+        if st != RX_OK:
+            raise RxError(st, "rx_dn_train_step")

@@ -78,6 +78,10 @@ def _load():
         lib.oracle_gen_channels.argtypes = [ctypes.POINTER(_GenParams), ctypes.c_uint64, ctypes.c_int64,
                                             ctypes.c_int64, dp, dp, i32p, i32p, dp, dp]
         lib.oracle_gen_channels.restype = ctypes.c_int
+        lib.oracle_sync_metric.argtypes = [ctypes.POINTER(ctypes.c_int16), ctypes.c_int, ctypes.c_int64,
+                                           ctypes.c_int64, ctypes.POINTER(ctypes.c_int8), ctypes.c_int,
+                                           ctypes.c_int64, u64p, ctypes.POINTER(ctypes.c_int64)]
+        lib.oracle_sync_metric.restype = ctypes.c_int
         lib.oracle_fft_symbols.argtypes = [ctypes.POINTER(_Params), ctypes.POINTER(ctypes.c_int16),
                                            ctypes.c_int64, dp]
         lib.oracle_fft_symbols.restype = ctypes.c_int
@@ -258,3 +262,38 @@ def gen_channels(gp: GenParams, seed: int, first_row: int, rows: int, draws: boo
     if draws:
         return ht, hl, {"n_taps": nt, "delays": dl, "taps": tp, "snr_db": sn}
     return ht, hl
+
+
+
+def sync_metric(raw: np.ndarray, pn, n_search: int, n_samples: Optional[int] = None):
+    """PN correlation metric M[n] (uint64, n < n_search) and the first offset of
+    its maximum for streams ``raw`` int16 [A][stride][2] whose first
+    ``n_samples`` samples are valid (default: all)."""
+    r = np.ascontiguousarray(raw, dtype=np.int16)
+    A, stride = r.shape[0], r.shape[1]
+    ns = stride if n_samples is None else int(n_samples)
+    chips = np.ascontiguousarray(np.asarray(pn).real, dtype=np.int8)
+    M = np.empty(n_search, dtype=np.uint64)
+    off = ctypes.c_int64()
+    st = _load().oracle_sync_metric(_ptr(r, ctypes.c_int16), A, ns, stride, _ptr(chips, ctypes.c_int8),
+                                    chips.size, n_search, _ptr(M, ctypes.c_uint64), ctypes.byref(off))
+    if st:
+        raise ValueError("oracle rejected the sync arguments")
+    return M, off.value
+
+
+def extract_slots(raw: np.ndarray, start: int, n_slots: int, n_sym: int, sym_len: int,
+                  n_samples: Optional[int] = None) -> np.ndarray:
+    """The receive path's input layout int16 [S][T][A][sym_len][2] cut from
+    streams ``raw`` [A][stride][2] beginning at sample ``start`` (symbols back to
+    back); samples outside [0, n_samples) read as zero."""
+    A, stride = raw.shape[0], raw.shape[1]
+    ns = stride if n_samples is None else int(n_samples)
+    out = np.zeros((n_slots, n_sym, A, sym_len, 2), dtype=np.int16)
+    for s in range(n_slots):
+        for t in range(n_sym):
+            i0 = start + (s * n_sym + t) * sym_len
+            lo, hi = max(i0, 0), min(i0 + sym_len, ns)
+            if hi > lo:
+                out[s, t, :, lo - i0:hi - i0] = raw[:, lo:hi]
+    return out

@@ -554,3 +554,45 @@ int oracle_gen_channels(const oracle_gen_params* g, uint64_t seed, int64_t first
   free(ht);
   return 0;
 }
+
+/* ---------------------------------------------------------------------------
+ * Frame synchronisation (paper Sec. III, implementation: the received
+ * baseband stream is correlated with the maximum-length PN sequence that
+ * opens every transmitted frame, and the correlation gives the offset of the
+ * first OFDM frame; Table I: PN length 255).
+ *
+ * Reading: chips p[m] in {-1, 0, +1}; for every candidate start n in
+ * [0, n_search) and every antenna a,
+ *   c_a[n] = sum_{m=0}^{L-1} p[m] y_a[n+m]        (complex, integer)
+ *   M[n]   = sum_a |c_a[n]|^2                      (non-coherent over antennas)
+ * in exact integer arithmetic; the offset is the first n at which M is
+ * largest.  y_a[i] is sample i of antenna a's stream (int16 I, Q), read at
+ * raw[(a * stride + i) * 2]; samples at i >= n_samples count as zero.
+ * ------------------------------------------------------------------------- */
+int oracle_sync_metric(const int16_t* raw, int n_ant, int64_t n_samples, int64_t stride, const int8_t* pn, int L,
+                       int64_t n_search, uint64_t* M, int64_t* offset) {
+  if (!raw || !pn || n_ant < 1 || L < 1 || n_search < 1 || n_samples < 0 || stride < n_samples) return -1;
+  int64_t best = -1;
+  uint64_t best_v = 0;
+  for (int64_t n = 0; n < n_search; n++) {
+    uint64_t acc = 0;
+    for (int a = 0; a < n_ant; a++) {
+      int64_t re = 0, im = 0;
+      for (int m = 0; m < L; m++) {
+        const int64_t i = n + m;
+        if (i >= n_samples) break;
+        const int16_t* s = raw + ((size_t)a * stride + i) * 2;
+        re += (int64_t)pn[m] * s[0];
+        im += (int64_t)pn[m] * s[1];
+      }
+      acc += (uint64_t)(re * re) + (uint64_t)(im * im);
+    }
+    if (M) M[n] = acc;
+    if (best < 0 || acc > best_v) {
+      best = n;
+      best_v = acc;
+    }
+  }
+  if (offset) *offset = best;
+  return 0;
+}

@@ -368,3 +368,88 @@ def init_denoiser_params(seed: int, last_scale: float = 0.1) -> np.ndarray:
             w *= last_scale
         out += [w.reshape(-1), np.zeros(co)]
     return np.concatenate(out).astype(np.float32)
+# Raw per-antenna streams with a PN preamble (frame synchronisation inputs).
+def pn_sequence(taps=(8, 6, 5, 4), length: int = 255, seed_state: int = 1) -> np.ndarray:
+    """Maximum-length sequence of a Fibonacci LFSR, chips mapped 0 -> +1, 1 -> -1.
+
+    Default feedback polynomial x^8 + x^6 + x^5 + x^4 + 1 (primitive), period 255.
+    """
+    n = max(taps)
+    state = [(seed_state >> i) & 1 for i in range(n)]  # state[0] is the output stage
+    out = np.empty(length, dtype=np.float64)
+    for i in range(length):
+        bit = state[0]
+        out[i] = 1.0 - 2.0 * bit
+        fb = 0
+        for t in taps:
+            fb ^= state[n - t]
+        state = state[1:] + [fb]
+    return out
+
+
+@dataclasses.dataclass
+class Stream:
+    """Received streams of every antenna: `raw` int16 [A][n_samples][2] holding
+    `lead` samples of noise, the PN preamble, then `frames.iq`'s slots back to
+    back.  `frames.iq` is exactly what cutting the aligned slots out of `raw`
+    must give."""
+    raw: np.ndarray
+    pn: np.ndarray     # complex128 [L], the preamble chips
+    lead: int          # samples before the preamble
+    frames: Frames
+    delays: np.ndarray  # channel tap delays (samples)
+
+
+def make_stream(cfg: FrameConfig, n_slots: int, lead: int, seed: int, tail: int = 64,
+                pn: Optional[np.ndarray] = None, snr_db: float = 10.0, channel: str = "rayleigh") -> Stream:
+    """One transmission: `lead` noise samples, the PN preamble (BPSK chips at the
+    OFDM signal's RMS), then `n_slots` OFDM slots, through one channel per
+    antenna constant over the stream ("rayleigh": the config's tapped-delay
+    profile; "flat": one Rayleigh tap at delay 0), AWGN with the per-subcarrier
+    SNR `snr_db` (as in make_frames), and one int16 gain for the whole stream."""
+    pn = pn_sequence() if pn is None else np.asarray(pn, dtype=np.complex128)
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
+    N, CP, T, A, U, b = cfg.fft_len, cfg.cp_len, cfg.n_sym, cfg.n_ant, cfg.n_used, cfg.bits_per_sym
+    bins = used_subcarrier_bins(N, U)
+    pilot = (1 - 2 * rng.integers(0, 2, size=U)).astype(np.complex128)
+    sym = []
+    bits_all, X_all = [], []
+    for _ in range(n_slots):
+        bits = rng.integers(0, 2, size=(T - 1, U, b), dtype=np.uint8)
+        X = qam_symbols(bits, b)
+        grid = np.zeros((T, N), dtype=np.complex128)
+        grid[0, bins] = pilot
+        grid[1:, bins] = X
+        x = np.fft.ifft(grid, axis=1) * math.sqrt(N)
+        sym.append(np.concatenate([x[:, N - CP:], x], axis=1).reshape(-1))
+        bits_all.append(bits)
+        X_all.append(X)
+    ofdm = np.concatenate(sym)
+    rms = math.sqrt(U / N)
+    x = np.concatenate([np.zeros(lead), pn * rms, ofdm, np.zeros(tail)])
+    if channel == "rayleigh":
+        delays, p = tap_delays_powers(cfg, rng.uniform(*cfg.tau_max_us) * 1e-6)
+    elif channel == "flat":
+        delays, p = np.zeros(1, dtype=np.int64), np.ones(1)
+    else:
+        raise ValueError(channel)
+    h = (rng.standard_normal((A, len(p))) + 1j * rng.standard_normal((A, len(p)))) * np.sqrt(p / 2.0)
+    y = np.zeros((A, x.size), dtype=np.complex128)
+    for l, dl in enumerate(delays):
+        y[:, dl:] += h[:, l:l + 1] * x[None, :x.size - dl]
+    sigma2 = 10.0 ** (-snr_db / 10.0)
+    y += (rng.standard_normal(y.shape) + 1j * rng.standard_normal(y.shape)) * math.sqrt(sigma2 / 2.0)
+    peak = max(np.abs(y.real).max(), np.abs(y.imag).max())
+    scale = 0.5 * INT16_FS / peak
+    q = np.rint(y * scale)
+    raw = np.empty((A, x.size, 2), dtype=np.int16)
+    raw[..., 0] = np.clip(q.real, -32768, 32767)
+    raw[..., 1] = np.clip(q.imag, -32768, 32767)
+    start = lead + len(pn)
+    sl = raw[:, start:start + n_slots * T * (N + CP)].reshape(A, n_slots, T, N + CP, 2)
+    iq = np.ascontiguousarray(sl.transpose(1, 2, 0, 3, 4))
+    ph = np.exp(-2j * np.pi * np.outer(bins, delays) / N)
+    H = np.broadcast_to((h @ ph.T) * (math.sqrt(N) * scale), (n_slots, A, U)).copy()
+    fr = Frames(cfg.replace(n_slots=n_slots), iq, pilot, np.stack(bits_all), np.stack(X_all), H,
+                np.full(n_slots, snr_db), np.full(n_slots, scale))
+    return Stream(raw, pn.astype(np.complex128), lead, fr, delays)

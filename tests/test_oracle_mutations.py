@@ -60,6 +60,11 @@ COMB_GEN_MUTANTS = {
     "gen_noise_block_shared": ("block_words(seed, row, noise_block + j / 2, b);",
                                "block_words(seed, row, 1 + j / 2, b);"),
     "gen_wrong_uniform": ("(double)(2 * (w >> 41) + 1) * 0x1p-24", "(double)((w >> 40) + 1) * 0x1p-24"),
+    "sync_last_maximum": ("if (best < 0 || acc > best_v) {", "if (best < 0 || acc >= best_v) {"),
+    "sync_drops_quadrature": ("acc += (uint64_t)(re * re) + (uint64_t)(im * im);", "acc += (uint64_t)(re * re);"),
+    "sync_chip_order_reversed": ("re += (int64_t)pn[m] * s[0];\n        im += (int64_t)pn[m] * s[1];",
+                                 "re += (int64_t)pn[L - 1 - m] * s[0];\n        im += (int64_t)pn[L - 1 - m] * s[1];"),
+    "sync_off_by_one": ("const int64_t i = n + m;", "const int64_t i = n + m + 1;"),
 }
 
 
@@ -81,7 +86,8 @@ def test_comb_and_generator_pins_catch_planted_mistake(name, tmp_path):
     env = dict(os.environ, RX_ORACLE_LIB=str(lib))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_comb.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_gen.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_gen.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_sync.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
     assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"
 

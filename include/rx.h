@@ -279,6 +279,43 @@ typedef struct {
 int rx_dn_generate(const rx_chan_gen* gen, uint64_t seed, int64_t first_row, int64_t rows, float* H_true,
                    float* H_ls, void* hip_stream);
 
+/* ---------------------------------------------------------------------------
+ * Frame synchronisation.  The transmitter opens a frame with a maximum-length
+ * PN sequence; the receiver correlates every antenna's stream with it and the
+ * correlation peak marks the frame start, from which the OFDM slots are cut
+ * (paper Sec. III, implementation; Table I: PN length 255).
+ *
+ * Streams: raw int16 [A][stride][2], antenna a's sample i at raw[(a*stride +
+ * i)*2] (I, Q); samples i >= n_samples (and i < 0) count as zero.
+ * Metric, in exact integer arithmetic, for candidate starts n < n_search:
+ *   c_a[n] = sum_{m<L} p[m] y_a[n+m],  M[n] = sum_a |c_a[n]|^2  (uint64)
+ * offset = the smallest n with the largest M[n].  Chips p[m] in {-1, 0, +1}.
+ * ------------------------------------------------------------------------- */
+#define RX_SYNC_MAX_PN 1024
+
+/* Device scratch of rx_sync_find: 16 bytes per 128 candidates. */
+size_t rx_sync_workspace_bytes(int64_t n_search);
+
+/* Correlation metric and peak.  raw: device, 4-byte aligned; 1 <= n_ant <= 4096;
+ * pn: HOST array of pn_len (1..RX_SYNC_MAX_PN) chips, copied into the launch;
+ * metric: device uint64 [n_search] or NULL; offset: device int64 [1]; peak:
+ * device uint64 [1] or NULL; workspace >= rx_sync_workspace_bytes(n_search),
+ * 256-byte aligned.  Asynchronous. */
+int rx_sync_find(const int16_t* raw, int32_t n_ant, int64_t n_samples, int64_t stride, const int8_t* pn,
+                 int32_t pn_len, int64_t n_search, uint64_t* metric, int64_t* offset, uint64_t* peak,
+                 void* workspace, void* hip_stream);
+
+/* Cut n_slots slots of n_sym symbols of sym_len (= CP + N) samples, back to
+ * back from stream sample (*start + start_add) (start: device int64 [1], e.g.
+ * rx_sync_find's offset, or NULL for 0), into iq int16 [n_slots][n_sym][A]
+ * [sym_len][2] (device, 4-byte aligned): the input layout of rx_estimate,
+ * rx_demod and rx_process_frame.  Out-of-stream samples are written as zero.
+ * For a preamble of L chips detected at offset o, start_add = L puts the first
+ * slot right after it. */
+int rx_sync_extract(const int16_t* raw, int32_t n_ant, int64_t n_samples, int64_t stride, const int64_t* start,
+                    int64_t start_add, int32_t sym_len, int32_t n_sym, int64_t n_slots, int16_t* iq,
+                    void* hip_stream);
+
 /* Static description of a status code. */
 const char* rx_status_string(int status);
 

@@ -38,14 +38,15 @@ def build(verbose: bool = False, save_temps: str | None = None) -> str:
         cmd = [cc, *COMMON, f"--offload-arch={ARCH}", "-c", os.path.join(CSRC, "rx_api.cpp"), "-o", api_o]
         _run(cmd, verbose)
         objs.append(api_o)
-        for name in ("rx_batch", "rx_dn_api"):
+        for name in ("rx_batch", "rx_dn_api", "rx_sync_api"):
             o = os.path.join(tmp, name + ".o")
             _run([cc, *COMMON, f"--offload-arch={ARCH}", "-c", os.path.join(CSRC, name + ".cpp"), "-o", o], verbose)
             objs.append(o)
-        dn_o = os.path.join(tmp, "rx_denoise.o")
-        _run([cc, *COMMON, f"--offload-arch={ARCH}", *DEVICE_FLAGS, "-x", "hip", "-c",
-              os.path.join(CSRC, "rx_denoise.hip"), "-o", dn_o], verbose)
-        objs.append(dn_o)
+        for name in ("rx_denoise", "rx_sync"):
+            o = os.path.join(tmp, name + ".o")
+            _run([cc, *COMMON, f"--offload-arch={ARCH}", *DEVICE_FLAGS, "-x", "hip", "-c",
+                  os.path.join(CSRC, name + ".hip"), "-o", o], verbose)
+            objs.append(o)
         k_o = os.path.join(tmp, "rx_kernels.o")
         cmd = [cc, *COMMON, f"--offload-arch={ARCH}", *DEVICE_FLAGS, "-x", "hip", "-c",
                os.path.join(CSRC, "rx_kernels.hip"), "-o", k_o]

@@ -103,4 +103,17 @@ hipError_t dn_train(const float2* Hin, const float2* Htrue, int64_t rows, int U,
 hipError_t dn_generate(const GenArgs& g, uint64_t seed, int64_t first_row, int64_t rows, float2* Htrue,
                        float2* Hls, hipStream_t st);
 
+// ---- PN frame synchronisation (rx_sync.hip)
+constexpr int kMaxPn = 1024;
+struct SyncChips {  // passed by value as a kernel argument
+  int L;
+  int8_t c[kMaxPn];
+};
+int64_t sync_blocks(int64_t n_search);
+hipError_t sync_find(const uint32_t* raw, int A, int64_t n_samples, int64_t stride, const SyncChips& ch,
+                     int64_t n_search, uint64_t* M, int64_t* offset, uint64_t* peak, void* workspace,
+                     hipStream_t st);
+hipError_t sync_extract(const uint32_t* raw, int A, int64_t n_samples, int64_t stride, const int64_t* start,
+                        int64_t start_add, int sym_len, int T, int64_t S, uint32_t* out, hipStream_t st);
+
 }  // namespace rx

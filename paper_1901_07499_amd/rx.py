@@ -26,7 +26,7 @@ EXPORTS = ("rx_params_check", "rx_plan_create", "rx_plan_destroy", "rx_workspace
            "rx_batch_create", "rx_batch_destroy", "rx_batch_layout", "rx_batch_workspace_bytes",
            "rx_batch_process", "rx_batch_autotune", "rx_batch_config", "rx_batch_frame_latency",
            "rx_dn_create", "rx_dn_destroy", "rx_dn_load", "rx_dn_apply", "rx_dn_workspace_bytes", "rx_dn_grad",
-           "rx_dn_train_step", "rx_dn_generate")
+           "rx_dn_train_step", "rx_dn_generate", "rx_sync_workspace_bytes", "rx_sync_find", "rx_sync_extract")
 RX_DN_PARAMS = 15330
 
 
@@ -94,9 +94,15 @@ def _load() -> ctypes.CDLL:
     lib.rx_dn_grad.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp]
     lib.rx_dn_train_step.argtypes = [vp, vp, vp, vp, i64, f32, f32, f32, f32, vp, vp, i64, vp, vp, vp]
     lib.rx_dn_generate.argtypes = [ctypes.POINTER(rx_chan_gen), ctypes.c_uint64, i64, i64, vp, vp, vp]
+    lib.rx_sync_workspace_bytes.argtypes = [i64]
+    lib.rx_sync_workspace_bytes.restype = sz
+    lib.rx_sync_find.argtypes = [vp, ctypes.c_int32, i64, i64, ctypes.POINTER(ctypes.c_int8), ctypes.c_int32, i64,
+                                 vp, vp, vp, vp, vp]
+    lib.rx_sync_extract.argtypes = [vp, ctypes.c_int32, i64, i64, vp, i64, ctypes.c_int32, ctypes.c_int32, i64, vp,
+                                    vp]
     for name in EXPORTS:
         if name not in ("rx_workspace_bytes", "rx_status_string", "rx_batch_workspace_bytes",
-                        "rx_dn_workspace_bytes"):
+                        "rx_dn_workspace_bytes", "rx_sync_workspace_bytes"):
             getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -211,6 +217,21 @@ def rx_dn_train_step(dn, params, m, v, step, lr, beta1, beta2, eps, H_in, H_true
 
 def rx_dn_generate(gen: rx_chan_gen, seed: int, first_row: int, rows: int, H_true, H_ls, stream) -> int:
     return _lib.rx_dn_generate(ctypes.byref(gen), seed, first_row, rows, H_true, H_ls, stream)
+
+
+def rx_sync_workspace_bytes(n_search: int) -> int:
+    return _lib.rx_sync_workspace_bytes(n_search)
+
+
+def rx_sync_find(raw, n_ant, n_samples, stride, pn, pn_len, n_search, metric, offset, peak, workspace,
+                 stream) -> int:
+    return _lib.rx_sync_find(raw, n_ant, n_samples, stride, pn, pn_len, n_search, metric, offset, peak, workspace,
+                             stream)
+
+
+def rx_sync_extract(raw, n_ant, n_samples, stride, start, start_add, sym_len, n_sym, n_slots, iq, stream) -> int:
+    return _lib.rx_sync_extract(raw, n_ant, n_samples, stride, start, start_add, sym_len, n_sym, n_slots, iq,
+                                stream)
 
 
 def make_params(n_ant: int, fft_len: int, cp_len: int, n_used: int, n_sym: int, bits_per_sym: int,
@@ -523,3 +544,48 @@ class Denoiser:
                               H.data_ptr(), H_true.data_ptr(), rows, _ptr(loss), ws.data_ptr(), self._stream())
         if st != RX_OK:
             raise RxError(st, "rx_dn_train_step")
+
+
+# ---------------------------------------------------------------- frame synchronisation
+def _chips(pn):
+    c = np.ascontiguousarray(np.rint(np.asarray(pn).real), dtype=np.int8)
+    return c, c.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))
+
+
+def sync_find(raw, pn, n_search: int, n_samples: Optional[int] = None, want_metric: bool = False):
+    """PN correlation over int16 CUDA streams ``raw`` [A][stride][2]: returns
+    (offset [1], peak [1], metric [n_search] or None) as int64 CUDA tensors;
+    peak and metric hold the library's uint64 values bit for bit."""
+    import torch
+    if raw.dtype != torch.int16 or raw.dim() != 3 or raw.shape[2] != 2 or not raw.is_contiguous() or not raw.is_cuda:
+        raise ValueError("raw must be a contiguous int16 CUDA tensor [A][stride][2]")
+    A, stride = raw.shape[0], raw.shape[1]
+    ns = stride if n_samples is None else int(n_samples)
+    chips, cp = _chips(pn)
+    dev = raw.device
+    off = torch.empty((1,), dtype=torch.int64, device=dev)
+    # uint64 values held in int64 tensors (view them as uint64 on the host)
+    peak = torch.empty((1,), dtype=torch.int64, device=dev)
+    M = torch.empty((n_search,), dtype=torch.int64, device=dev) if want_metric else None
+    ws = torch.empty((max(256, rx_sync_workspace_bytes(n_search)),), dtype=torch.uint8, device=dev)
+    st = rx_sync_find(raw.data_ptr(), A, ns, stride, cp, chips.size, n_search, _ptr(M), off.data_ptr(),
+                      peak.data_ptr(), ws.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    if st != RX_OK:
+        raise RxError(st, "rx_sync_find")
+    return off, peak, M
+
+
+def sync_extract(raw, start, start_add: int, sym_len: int, n_sym: int, n_slots: int,
+                 n_samples: Optional[int] = None, out=None):
+    """Slots cut from the streams at (*start + start_add): int16 CUDA tensor
+    [n_slots][n_sym][A][sym_len][2] (``start``: int64 CUDA tensor [1] or None)."""
+    import torch
+    A, stride = raw.shape[0], raw.shape[1]
+    ns = stride if n_samples is None else int(n_samples)
+    if out is None:
+        out = torch.empty((n_slots, n_sym, A, sym_len, 2), dtype=torch.int16, device=raw.device)
+    st = rx_sync_extract(raw.data_ptr(), A, ns, stride, _ptr(start), start_add, sym_len, n_sym, n_slots,
+                         out.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    if st != RX_OK:
+        raise RxError(st, "rx_sync_extract")
+    return out

@@ -280,14 +280,95 @@ def bench_denoiser(args):
     print(json.dumps(rec), flush=True)
 
 
+# Integer multiply-adds per CU per clock of the vector ALU (64-wide wavefronts,
+# four SIMDs; the FP32 rate without packed instructions), 256 CUs at 2.4 GHz.
+VALU_INT_MAC_PEAK = 256 * 64 * 2.4e9
+
+
+def bench_sync(args):
+    """PN synchronisation on a stream of the 64-antenna, N=1024 shape: a
+    255-chip preamble at a random offset, then `--slots` slots; time the
+    correlation metric over one slot's worth of candidate offsets, the slot
+    extraction, and sync + extraction + receive."""
+    import numpy as np
+    from rxgen import C2, make_stream
+    S = args.slots
+    t0 = time.time()
+    lead = 5000
+    st = make_stream(C2.replace(name="c2_stream"), S, lead, seed=190107499 + 7, snr_db=20.0)
+    cfg = st.frames.cfg
+    log(f"generated a {cfg.n_ant}-antenna stream of {st.raw.shape[1]} samples with {S} slots in {time.time() - t0:.1f} s")
+    import torch
+    from paper_1901_07499_amd import rx
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    raw = torch.from_numpy(st.raw).to(dev)
+    A, L, T = cfg.n_ant, st.pn.size, cfg.n_sym
+    sym_len = cfg.fft_len + cfg.cp_len
+    n_search = T * sym_len
+    plan = rx.Plan.from_config(cfg, st.frames.pilot)
+    iq = torch.empty((S, T, A, sym_len, 2), dtype=torch.int16, device=dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, reps):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    box = {}
+
+    def find():
+        box["off"] = rx.sync_find(raw, st.pn, n_search)[0]
+
+    find_ms = timed(find, args.steps)
+    off = box["off"]
+    ext_ms = timed(lambda: rx.sync_extract(raw, off, L, sym_len, T, S, out=iq), args.steps)
+
+    def chain():
+        o = rx.sync_find(raw, st.pn, n_search)[0]
+        rx.sync_extract(raw, o, L, sym_len, T, S, out=iq)
+        return plan.process(iq)
+
+    chain_ms = timed(chain, args.steps)
+    _, _, bits = chain()
+    torch.cuda.synchronize()
+    sent = np.unpackbits(st.frames.packed_bits(), axis=-1)
+    errs = int(np.count_nonzero(np.unpackbits(bits.cpu().numpy(), axis=-1) != sent))
+    macs = 2.0 * A * n_search * L
+    ext_bytes = 2 * S * T * A * sym_len * 4
+    samples = S * T * A * sym_len
+    rec = {"metric": "antenna-samples/s through PN sync + slot extraction + FFT+LS+demod", "value": samples / (chain_ms * 1e-3),
+           "unit": "antenna-samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": chain_ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "int32 metric, f32 path", "data": "synthetic",
+           "config": {"workload": "c2_stream_pn255", "n_ant": A, "fft_len": cfg.fft_len, "cp_len": cfg.cp_len,
+                      "n_slots": S, "pn_len": int(L), "n_search": n_search, "lead": lead},
+           "roofline": {"bound": "alu", "kernel": "sync_metric_kernel",
+                        "achieved": round(macs / (find_ms * 1e-3) / 1e12, 3),
+                        "peak": round(VALU_INT_MAC_PEAK / 1e12, 3), "unit": "T int-MAC/s",
+                        "frac": round(macs / (find_ms * 1e-3) / VALU_INT_MAC_PEAK, 4), "traffic": None,
+                        "algorithmic_macs_per_launch": macs, "avg_launch_ms": round(find_ms, 5)},
+           "sync_find_ms": round(find_ms, 5), "extract_ms": round(ext_ms, 5),
+           "extract_GBps": round(ext_bytes / (ext_ms * 1e-3) / 1e9, 1),
+           "offset": int(off.item()), "lead": lead, "bit_errors": errs, "bits": int(sent.size),
+           "kernel_hash": kernel_hash()}
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4", "batch", "denoiser"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4", "batch", "denoiser", "sync"])
     ap.add_argument("--frames", type=int, default=256, help="frames of the batch workload")
-    ap.add_argument("--slots", type=int, default=32, help="slots of the denoiser workload")
+    ap.add_argument("--slots", type=int, default=32, help="slots of the denoiser and sync workloads")
     ap.add_argument("--quality-slots", type=int, default=8, help="slots per SNR of the denoiser quality figures")
     ap.add_argument("--dn-steps", type=int, default=2000, help="training steps of the denoiser workload")
     ap.add_argument("--dn-rows", type=int, default=256, help="rows (antenna estimates) per training step")
@@ -320,6 +401,9 @@ def main():
         return
     if args.workload == "denoiser":
         bench_denoiser(args)
+        return
+    if args.workload == "sync":
+        bench_sync(args)
         return
     from rxgen import C1, C2, C2_20DB, C4, make_frames
     cfg = {"c1": C1, "c2": C2, "c4": C4}[args.workload]

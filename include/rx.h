@@ -283,7 +283,7 @@ int rx_dn_generate(const rx_chan_gen* gen, uint64_t seed, int64_t first_row, int
  * Frame synchronisation.  The transmitter opens a frame with a maximum-length
  * PN sequence; the receiver correlates every antenna's stream with it and the
  * correlation peak marks the frame start, from which the OFDM slots are cut
- * (paper Sec. III, implementation; Table I: PN length 255).
+ * (paper Sec. II-B, implementation outline; Table I: PN length 255).
  *
  * Streams: raw int16 [A][stride][2], antenna a's sample i at raw[(a*stride +
  * i)*2] (I, Q); samples i >= n_samples (and i < 0) count as zero.

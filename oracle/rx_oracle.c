@@ -556,7 +556,7 @@ int oracle_gen_channels(const oracle_gen_params* g, uint64_t seed, int64_t first
 }
 
 /* ---------------------------------------------------------------------------
- * Frame synchronisation (paper Sec. III, implementation: the received
+ * Frame synchronisation (paper Sec. II-B, implementation outline: the received
  * baseband stream is correlated with the maximum-length PN sequence that
  * opens every transmitted frame, and the correlation gives the offset of the
  * first OFDM frame; Table I: PN length 255).

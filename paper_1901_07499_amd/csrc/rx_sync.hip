@@ -2,7 +2,7 @@
 //
 // The receiver correlates every antenna's stream with the maximum-length PN
 // sequence that opens a frame and takes the correlation peak as the start of
-// the frame (paper Sec. III; Table I: PN length 255):
+// the frame (paper Sec. II-B; Table I: PN length 255):
 //   c_a[n] = sum_m p[m] y_a[n+m],   M[n] = sum_a |c_a[n]|^2,
 //   offset = the first n with the largest M[n].
 // With chips p in {-1, 0, +1} and int16 samples the metric is exact in

@@ -2,7 +2,7 @@
 
 The paper correlates the received stream with the maximum-length PN sequence
 (length 255, Table I) that opens each frame and takes the correlation peak as
-the offset of the first OFDM frame (Sec. III).  Pins: the m-sequence's
+the offset of the first OFDM frame (Sec. II-B).  Pins: the m-sequence's
 defining properties; the metric against numpy's correlate (a library routine)
 and closed forms; shift equivariance; the first-maximum rule; and extraction
 against the transmitter's own slot buffer.

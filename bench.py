@@ -349,7 +349,7 @@ def bench_sync(args):
            "dtype": "int32 metric, f32 path", "data": "synthetic",
            "config": {"workload": "c2_stream_pn255", "n_ant": A, "fft_len": cfg.fft_len, "cp_len": cfg.cp_len,
                       "n_slots": S, "pn_len": int(L), "n_search": n_search, "lead": lead},
-           "roofline": {"bound": "alu", "kernel": "sync_metric_kernel",
+           "roofline": {"bound": "alu", "kernel": "rx_sync_find (metric, group sum, argmax)",
                         "achieved": round(macs / (find_ms * 1e-3) / 1e12, 3),
                         "peak": round(VALU_INT_MAC_PEAK / 1e12, 3), "unit": "T int-MAC/s",
                         "frac": round(macs / (find_ms * 1e-3) / VALU_INT_MAC_PEAK, 4), "traffic": None,

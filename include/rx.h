@@ -293,13 +293,16 @@ int rx_dn_generate(const rx_chan_gen* gen, uint64_t seed, int64_t first_row, int
  * ------------------------------------------------------------------------- */
 #define RX_SYNC_MAX_PN 1024
 
-/* Device scratch of rx_sync_find: 16 bytes per 128 candidates. */
-size_t rx_sync_workspace_bytes(int64_t n_search);
+/* Device scratch of rx_sync_find for n_ant antennas and n_search candidates
+ * (per-antenna-group partial metrics and per-block maxima; at most
+ * 64 * 8 * n_search bytes plus 16 per 256 candidates).  0 on bad arguments. */
+size_t rx_sync_workspace_bytes(int32_t n_ant, int64_t n_search);
 
 /* Correlation metric and peak.  raw: device, 4-byte aligned; 1 <= n_ant <= 4096;
+ * 1 <= n_search <= 2^36;
  * pn: HOST array of pn_len (1..RX_SYNC_MAX_PN) chips, copied into the launch;
  * metric: device uint64 [n_search] or NULL; offset: device int64 [1]; peak:
- * device uint64 [1] or NULL; workspace >= rx_sync_workspace_bytes(n_search),
+ * device uint64 [1] or NULL; workspace >= rx_sync_workspace_bytes(n_ant, n_search),
  * 256-byte aligned.  Asynchronous. */
 int rx_sync_find(const int16_t* raw, int32_t n_ant, int64_t n_samples, int64_t stride, const int8_t* pn,
                  int32_t pn_len, int64_t n_search, uint64_t* metric, int64_t* offset, uint64_t* peak,

@@ -109,7 +109,8 @@ struct SyncChips {  // passed by value as a kernel argument
   int L;
   int8_t c[kMaxPn];
 };
-int64_t sync_blocks(int64_t n_search);
+int sync_groups(int A, int64_t n_search);
+size_t sync_workspace(int A, int64_t n_search);
 hipError_t sync_find(const uint32_t* raw, int A, int64_t n_samples, int64_t stride, const SyncChips& ch,
                      int64_t n_search, uint64_t* M, int64_t* offset, uint64_t* peak, void* workspace,
                      hipStream_t st);

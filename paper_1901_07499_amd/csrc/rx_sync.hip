@@ -9,12 +9,14 @@
 // integers (|c| < 2^25 per component, M < 2^64), so the peak decision needs no
 // floating point at all.
 //
-// sync_metric_kernel: one thread per candidate n; a workgroup stages the
-// samples its candidates need (kCand + L - 1 per antenna) in LDS and loops over
-// the antennas in order, so M[n] is a fixed-order integer sum.  Each workgroup
-// also reduces its (M, n) pairs to the best one; sync_argmax_kernel reduces
-// those in one workgroup.  "Best" = larger M, then smaller n: a total order,
-// so the result does not depend on the reduction order.
+// sync_metric_kernel: workgroup = (1024 candidates, group of antennas); per
+// antenna the workgroup stages the samples its candidates need in LDS and
+// each thread correlates 4 consecutive candidates through a sliding register
+// window.  The per-group partial metrics are summed by sync_reduce_kernel
+// (integer sums: exact in any order), which also reduces each 256 candidates
+// to the best (M, n); sync_argmax_kernel reduces those in one workgroup.
+// "Best" = larger M, then smaller n: a total order, so the result does not
+// depend on the reduction order.
 // sync_extract_kernel: copies the slots that follow the preamble into the
 // receive path's layout [S][T][A][CP+N] (one complex sample per dword); the
 // start index is read from device memory (the detected offset) plus a
@@ -27,7 +29,9 @@
 namespace rx {
 namespace sync {
 
-constexpr int kCand = 128;  // candidates (threads) per workgroup
+constexpr int kThreads = 256;       // threads per metric workgroup
+constexpr int kTile = 4 * kThreads;  // candidates per metric workgroup
+constexpr int kMaxGroups = 64;       // antenna groups (grid.y) at most
 
 struct Best {
   uint64_t v;
@@ -58,41 +62,98 @@ __device__ __forceinline__ Best block_best(Best b, Best* sh) {
   return b;
 }
 
-__global__ __launch_bounds__(kCand) void sync_metric_kernel(const uint32_t* __restrict__ raw, int A,
-                                                            int64_t n_samples, int64_t stride, SyncChips ch,
-                                                            int64_t n_search, uint64_t* __restrict__ M,
-                                                            uint64_t* __restrict__ cand_v,
-                                                            int64_t* __restrict__ cand_i) {
-  extern __shared__ uint32_t ys[];  // [kCand + L - 1]
-  __shared__ int chip[kMaxPn];
-  __shared__ Best sh[kCand / 64];
+// Partial metric of one antenna group for kTile candidates: thread t owns
+// candidates n0 + 4t .. n0 + 4t + 3 and slides a 4-sample register window
+// along the staged samples, so each LDS read feeds 4 (candidate, chip) pairs.
+template <int Q>
+__device__ __forceinline__ void unpack(uint32_t s, int (&re)[Q], int (&im)[Q], int j) {
+  re[j] = (int)(int16_t)(s & 0xFFFFu);
+  im[j] = (int)(int16_t)(s >> 16);
+}
+
+__global__ __launch_bounds__(kThreads) void sync_metric_kernel(const uint32_t* __restrict__ raw, int A, int ag,
+                                                               int64_t n_samples, int64_t stride, SyncChips ch,
+                                                               int64_t n_search, uint64_t* __restrict__ part) {
+  extern __shared__ uint32_t ys[];  // [kTile + L + 3]
   const int tid = threadIdx.x, L = ch.L;
-  const int64_t n0 = (int64_t)blockIdx.x * kCand, n = n0 + tid;
-  for (int m = tid; m < L; m += kCand) chip[m] = ch.c[m];
-  const int span = kCand + L - 1;
-  uint64_t acc = 0;
-  for (int a = 0; a < A; a++) {
-    __syncthreads();  // the previous antenna's readers are done (and the chips are in place)
+  const int64_t n0 = (int64_t)blockIdx.x * kTile;
+  const int g = blockIdx.y, a0 = g * ag, a1 = min(A, a0 + ag);
+  const int span = kTile + L + 3;
+  uint64_t acc[4] = {0, 0, 0, 0};
+  for (int a = a0; a < a1; a++) {
+    __syncthreads();  // the previous antenna's readers are done
     const uint32_t* ya = raw + (int64_t)a * stride;
-    for (int j = tid; j < span; j += kCand) {
+    for (int j = tid; j < span; j += kThreads) {
       const int64_t i = n0 + j;
       ys[j] = i < n_samples ? ya[i] : 0u;
     }
     __syncthreads();
-    int re = 0, im = 0;
-    for (int m = 0; m < L; m++) {
-      const uint32_t s = ys[tid + m];
-      const int c = chip[m];
-      re += c * (int)(int16_t)(s & 0xFFFFu);
-      im += c * (int)(int16_t)(s >> 16);
+    const uint32_t* y = ys + 4 * tid;
+    int wr[4], wi[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) unpack<4>(y[j], wr, wi, j);
+    int re[4] = {0, 0, 0, 0}, im[4] = {0, 0, 0, 0};
+    // window slot (m + j) % 4 holds sample 4t + m + j
+    int m = 0;
+    for (; m + 4 <= L; m += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const int c = ch.c[m + u];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          re[j] += c * wr[(u + j) & 3];
+          im[j] += c * wi[(u + j) & 3];
+        }
+        unpack<4>(y[m + u + 4], wr, wi, u);  // slot u now holds sample 4t + m + u + 4
+      }
     }
-    acc += (uint64_t)((int64_t)re * re) + (uint64_t)((int64_t)im * im);
+    for (; m < L; m++) {  // tail: rotate by hand
+      const int c = ch.c[m];
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const int s = (m + j) & 3;
+        int vr = wr[0], vi = wi[0];
+#pragma unroll
+        for (int k = 1; k < 4; k++)
+          if (s == k) {
+            vr = wr[k];
+            vi = wi[k];
+          }
+        re[j] += c * vr;
+        im[j] += c * vi;
+      }
+      const int s = m & 3;
+      const uint32_t nx = y[m + 4];
+#pragma unroll
+      for (int k = 0; k < 4; k++)
+        if (s == k) unpack<4>(nx, wr, wi, k);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; j++) acc[j] += (uint64_t)((int64_t)re[j] * re[j]) + (uint64_t)((int64_t)im[j] * im[j]);
   }
+  uint64_t* out = part + (int64_t)g * n_search;
+#pragma unroll
+  for (int j = 0; j < 4; j++) {
+    const int64_t n = n0 + 4 * tid + j;
+    if (n < n_search) out[n] = acc[j];
+  }
+}
+
+// M[n] = sum over antenna groups (integers: any order is exact), plus the
+// best (M, n) of each workgroup.
+__global__ __launch_bounds__(256) void sync_reduce_kernel(const uint64_t* __restrict__ part, int G, int64_t n_search,
+                                                          uint64_t* __restrict__ M, uint64_t* __restrict__ cand_v,
+                                                          int64_t* __restrict__ cand_i) {
+  __shared__ Best sh[4];
+  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const bool ok = n < n_search;
-  if (ok && M) M[n] = acc;
-  Best b = {ok ? acc : 0ull, ok ? n : INT64_MAX};
+  uint64_t v = 0;
+  if (ok)
+    for (int g = 0; g < G; g++) v += part[(int64_t)g * n_search + n];
+  if (ok && M) M[n] = v;
+  Best b = {ok ? v : 0ull, ok ? n : INT64_MAX};
   b = block_best(b, sh);
-  if (tid == 0) {
+  if (threadIdx.x == 0) {
     cand_v[blockIdx.x] = b.v;
     cand_i[blockIdx.x] = b.i;
   }
@@ -135,19 +196,41 @@ __global__ __launch_bounds__(256) void sync_extract_kernel(const uint32_t* __res
 
 }  // namespace sync
 
-int64_t sync_blocks(int64_t n_search) { return (n_search + sync::kCand - 1) / sync::kCand; }
+// Antenna groups: enough workgroups to fill the GPU (about 512), at most one
+// group per antenna.
+int sync_groups(int A, int64_t n_search) {
+  const int64_t tiles = (n_search + sync::kTile - 1) / sync::kTile;
+  int64_t g = (512 + tiles - 1) / tiles;
+  if (g > A) g = A;
+  if (g > sync::kMaxGroups) g = sync::kMaxGroups;
+  if (g < 1) g = 1;
+  const int ag = (A + (int)g - 1) / (int)g;
+  return (A + ag - 1) / ag;
+}
+
+size_t sync_workspace(int A, int64_t n_search) {
+  const int64_t nb = (n_search + 255) / 256;
+  return (size_t)sync_groups(A, n_search) * n_search * 8 + (size_t)nb * 16;
+}
 
 hipError_t sync_find(const uint32_t* raw, int A, int64_t n_samples, int64_t stride, const SyncChips& ch,
                      int64_t n_search, uint64_t* M, int64_t* offset, uint64_t* peak, void* workspace,
                      hipStream_t st) {
-  const int64_t nb = sync_blocks(n_search);
-  uint64_t* cv = static_cast<uint64_t*>(workspace);
+  const int G = sync_groups(A, n_search);
+  const int ag = (A + G - 1) / G;
+  const int64_t tiles = (n_search + sync::kTile - 1) / sync::kTile;
+  const int64_t nb = (n_search + 255) / 256;
+  uint64_t* part = static_cast<uint64_t*>(workspace);
+  uint64_t* cv = part + (int64_t)G * n_search;
   int64_t* ci = reinterpret_cast<int64_t*>(cv + nb);
-  const size_t lds = sizeof(uint32_t) * (size_t)(sync::kCand + ch.L - 1);
-  hipLaunchKernelGGL(sync::sync_metric_kernel, dim3((unsigned)nb), dim3(sync::kCand), lds, st, raw, A, n_samples,
-                     stride, ch, n_search, M, cv, ci);
+  const size_t lds = sizeof(uint32_t) * (size_t)(sync::kTile + ch.L + 3);
+  hipLaunchKernelGGL(sync::sync_metric_kernel, dim3((unsigned)tiles, (unsigned)G), dim3(sync::kThreads), lds, st,
+                     raw, A, ag, n_samples, stride, ch, n_search, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(sync::sync_reduce_kernel, dim3((unsigned)nb), dim3(256), 0, st, (const uint64_t*)part, G,
+                     n_search, M, cv, ci);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(sync::sync_argmax_kernel, dim3(1), dim3(256), 0, st, (const uint64_t*)cv, (const int64_t*)ci,
                      (int)nb, offset, peak);
   return hipGetLastError();

@@ -25,9 +25,9 @@ int check_streams(const int16_t* raw, int32_t n_ant, int64_t n_samples, int64_t 
 
 extern "C" {
 
-size_t rx_sync_workspace_bytes(int64_t n_search) {
-  if (n_search < 1) return 0;
-  return (size_t)rx::sync_blocks(n_search) * 16;
+size_t rx_sync_workspace_bytes(int32_t n_ant, int64_t n_search) {
+  if (n_search < 1 || n_ant < 1 || n_ant > 4096 || n_search > (INT64_C(1) << 36)) return 0;
+  return rx::sync_workspace(n_ant, n_search);
 }
 
 int rx_sync_find(const int16_t* raw, int32_t n_ant, int64_t n_samples, int64_t stride, const int8_t* pn,
@@ -36,7 +36,7 @@ int rx_sync_find(const int16_t* raw, int32_t n_ant, int64_t n_samples, int64_t s
   int st = check_streams(raw, n_ant, n_samples, stride);
   if (st != RX_OK) return st;
   if (!pn || pn_len < 1 || pn_len > RX_SYNC_MAX_PN) return RX_E_INVALID_ARG;
-  if (n_search < 1 || rx::sync_blocks(n_search) > INT64_C(0x7fffffff)) return RX_E_INVALID_ARG;
+  if (n_search < 1 || n_search > (INT64_C(1) << 36)) return RX_E_INVALID_ARG;
   if (!offset || !aligned(offset, 8) || (metric && !aligned(metric, 8)) || (peak && !aligned(peak, 8)))
     return RX_E_INVALID_ARG;
   if (!workspace || !aligned(workspace, 256)) return RX_E_INVALID_ARG;

@@ -94,7 +94,7 @@ def _load() -> ctypes.CDLL:
     lib.rx_dn_grad.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp]
     lib.rx_dn_train_step.argtypes = [vp, vp, vp, vp, i64, f32, f32, f32, f32, vp, vp, i64, vp, vp, vp]
     lib.rx_dn_generate.argtypes = [ctypes.POINTER(rx_chan_gen), ctypes.c_uint64, i64, i64, vp, vp, vp]
-    lib.rx_sync_workspace_bytes.argtypes = [i64]
+    lib.rx_sync_workspace_bytes.argtypes = [ctypes.c_int32, i64]
     lib.rx_sync_workspace_bytes.restype = sz
     lib.rx_sync_find.argtypes = [vp, ctypes.c_int32, i64, i64, ctypes.POINTER(ctypes.c_int8), ctypes.c_int32, i64,
                                  vp, vp, vp, vp, vp]
@@ -219,8 +219,8 @@ def rx_dn_generate(gen: rx_chan_gen, seed: int, first_row: int, rows: int, H_tru
     return _lib.rx_dn_generate(ctypes.byref(gen), seed, first_row, rows, H_true, H_ls, stream)
 
 
-def rx_sync_workspace_bytes(n_search: int) -> int:
-    return _lib.rx_sync_workspace_bytes(n_search)
+def rx_sync_workspace_bytes(n_ant: int, n_search: int) -> int:
+    return _lib.rx_sync_workspace_bytes(n_ant, n_search)
 
 
 def rx_sync_find(raw, n_ant, n_samples, stride, pn, pn_len, n_search, metric, offset, peak, workspace,
@@ -567,7 +567,7 @@ def sync_find(raw, pn, n_search: int, n_samples: Optional[int] = None, want_metr
     # uint64 values held in int64 tensors (view them as uint64 on the host)
     peak = torch.empty((1,), dtype=torch.int64, device=dev)
     M = torch.empty((n_search,), dtype=torch.int64, device=dev) if want_metric else None
-    ws = torch.empty((max(256, rx_sync_workspace_bytes(n_search)),), dtype=torch.uint8, device=dev)
+    ws = torch.empty((max(256, rx_sync_workspace_bytes(A, n_search)),), dtype=torch.uint8, device=dev)
     st = rx_sync_find(raw.data_ptr(), A, ns, stride, cp, chips.size, n_search, _ptr(M), off.data_ptr(),
                       peak.data_ptr(), ws.data_ptr(), torch.cuda.current_stream().cuda_stream)
     if st != RX_OK:

@@ -76,6 +76,20 @@ enum rx_status {
 
 enum rx_combiner { RX_COMB_MRC = 0, RX_COMB_ZF = 1 };
 
+/* FFT arithmetic.  RX_FFT_RADIX_F32: Stockham radix FFT in FP32 on the vector
+ * units (every N).  The MFMA modes (N = 2048, U <= 1536, MRC, block pilot
+ * only) recast the transform as 2048 = 8 x 16 x 16: an FP32 radix-8 stage,
+ * then two 16-point DFT stages as GEMMs on the fp16 or bf16 matrix cores
+ * with FP32 accumulation; _SPLIT also splits both GEMM operands into
+ * hi + lo parts and sums the three significant products. */
+enum rx_fft_mode {
+  RX_FFT_RADIX_F32 = 0,
+  RX_FFT_MFMA_F16 = 1,
+  RX_FFT_MFMA_BF16 = 2,
+  RX_FFT_MFMA_F16_SPLIT = 3,
+  RX_FFT_MFMA_BF16_SPLIT = 4
+};
+
 typedef struct {
   int32_t n_ant;        /* A >= 1 receive antennas */
   int32_t fft_len;      /* N, a power of two in [64, 2048] */
@@ -96,6 +110,7 @@ typedef struct {
                             the last pilot that pilot's value is held.  The comb form is
                             the standard LS-with-interpolation estimator the learned
                             refinement below starts from.  Batches need 0 or 1. */
+  int32_t fft_mode;      /* enum rx_fft_mode; 0 = FP32 radix (batches need 0) */
 } rx_params;
 
 /* Validate parameters without touching the GPU.  Returns RX_OK or the status

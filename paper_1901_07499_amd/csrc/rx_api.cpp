@@ -48,6 +48,10 @@ int check_params(const rx_params* p) {
   if (p->combiner != RX_COMB_MRC && p->combiner != RX_COMB_ZF) return RX_E_UNSUPPORTED;
   if (!p->pilot) return RX_E_INVALID_ARG;
   if (p->pilot_spacing < 0 || p->pilot_spacing > p->n_used) return RX_E_INVALID_ARG;
+  if (p->fft_mode < RX_FFT_RADIX_F32 || p->fft_mode > RX_FFT_MFMA_BF16_SPLIT) return RX_E_UNSUPPORTED;
+  if (p->fft_mode != RX_FFT_RADIX_F32 &&
+      (p->fft_len != 2048 || p->n_used > 1536 || p->combiner != RX_COMB_MRC || p->pilot_spacing > 1))
+    return RX_E_UNSUPPORTED;
   for (int d = 0; d < p->n_used; d += spacing(*p)) {
     const float re = p->pilot[2 * d], im = p->pilot[2 * d + 1];
     if (!std::isfinite(re) || !std::isfinite(im) || (re == 0.0f && im == 0.0f)) return RX_E_INVALID_ARG;
@@ -91,6 +95,7 @@ rx::LaunchArgs launch_args(rx_plan_t plan, const int16_t* iq, int64_t S, void* s
   la.tw = plan->tw;
   la.pf = plan->pf;
   la.ps = spacing(plan->p);
+  la.fft_mode = plan->p.fft_mode;
   la.stream = reinterpret_cast<hipStream_t>(stream);
   return la;
 }

@@ -296,7 +296,7 @@ int rx_batch_create(const rx_params* frames, int32_t n_frames, rx_batch_t* out) 
     const int st = rx_params_check(&frames[i]);
     if (st != RX_OK) return st;
     if (frames[i].combiner != RX_COMB_MRC) return RX_E_UNSUPPORTED;
-    if (frames[i].pilot_spacing > 1) return RX_E_UNSUPPORTED;
+    if (frames[i].pilot_spacing > 1 || frames[i].fft_mode != 0) return RX_E_UNSUPPORTED;
   }
   rx_batch_s* b = new (std::nothrow) rx_batch_s;
   if (!b) return RX_E_NOMEM;

@@ -620,6 +620,7 @@ hipError_t demod_dispatch(const LaunchArgs& la, const float2* H, float2* xhat, u
 }  // namespace
 
 hipError_t launch_estimate(const LaunchArgs& la, float2* H) {
+  if (la.fft_mode != 0) return launch_mfma_estimate(la, H);
   switch (la.N) {
     case 64: return estimate_n<64>(la, H);
     case 128: return estimate_n<128>(la, H);
@@ -639,10 +640,12 @@ hipError_t launch_g(const LaunchArgs& la, const float2* H, float* g) {
 }
 
 hipError_t launch_demod(const LaunchArgs& la, bool zf, const float2* H, float2* xhat, uint8_t* bits) {
+  if (la.fft_mode != 0) return launch_mfma_demod(la, H, xhat, bits);
   return zf ? demod_dispatch<true>(la, H, xhat, bits) : demod_dispatch<false>(la, H, xhat, bits);
 }
 
 hipError_t launch_fft(const LaunchArgs& la, float2* Y) {
+  if (la.fft_mode != 0) return launch_mfma_fft(la, Y);
   switch (la.N) {
     case 64: return fft_n<64>(la, Y);
     case 128: return fft_n<128>(la, Y);

@@ -14,8 +14,14 @@ struct LaunchArgs {
   const float2* tw;    // tw[k] = exp(-2 pi i k / N), k < N
   const float2* pf;    // pf[d] = conj(Xp[d]) / |Xp[d]|^2 (pilot subcarriers only)
   int ps;              // pilot spacing: 1 = block pilot, > 1 = comb on d % ps == 0
+  int fft_mode;        // enum rx_fft_mode
   hipStream_t stream;
 };
+
+// MFMA DFT-GEMM path (rx_mfma_fft.hip), N = 2048, fft_mode 1..4.
+hipError_t launch_mfma_estimate(const LaunchArgs& la, float2* H);
+hipError_t launch_mfma_demod(const LaunchArgs& la, const float2* H, float2* xhat, uint8_t* bits);
+hipError_t launch_mfma_fft(const LaunchArgs& la, float2* Y);
 
 hipError_t launch_estimate(const LaunchArgs& la, float2* H);
 hipError_t launch_g(const LaunchArgs& la, const float2* H, float* g);

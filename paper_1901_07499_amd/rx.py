@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(_HERE, "librx.so")
 
 RX_OK, RX_E_INVALID_ARG, RX_E_UNSUPPORTED, RX_E_HIP, RX_E_NOMEM = 0, -1, -2, -3, -4
 RX_COMB_MRC, RX_COMB_ZF = 0, 1
+RX_FFT_RADIX_F32, RX_FFT_MFMA_F16, RX_FFT_MFMA_BF16, RX_FFT_MFMA_F16_SPLIT, RX_FFT_MFMA_BF16_SPLIT = 0, 1, 2, 3, 4
+FFT_MODES = {"f32": 0, "f16": 1, "bf16": 2, "f16_split": 3, "bf16_split": 4}
 
 # Every symbol the header declares; the CPU test checks they are all exported.
 EXPORTS = ("rx_params_check", "rx_plan_create", "rx_plan_destroy", "rx_workspace_bytes", "rx_estimate",
@@ -47,7 +49,8 @@ class rx_params(ctypes.Structure):
     _fields_ = [("n_ant", ctypes.c_int32), ("fft_len", ctypes.c_int32), ("cp_len", ctypes.c_int32),
                 ("n_used", ctypes.c_int32), ("n_sym", ctypes.c_int32), ("bits_per_sym", ctypes.c_int32),
                 ("combiner", ctypes.c_int32), ("n_users", ctypes.c_int32),
-                ("pilot", ctypes.POINTER(ctypes.c_float)), ("pilot_spacing", ctypes.c_int32)]
+                ("pilot", ctypes.POINTER(ctypes.c_float)), ("pilot_spacing", ctypes.c_int32),
+                ("fft_mode", ctypes.c_int32)]
 
 
 def _load() -> ctypes.CDLL:
@@ -235,11 +238,12 @@ def rx_sync_extract(raw, n_ant, n_samples, stride, start, start_add, sym_len, n_
 
 
 def make_params(n_ant: int, fft_len: int, cp_len: int, n_used: int, n_sym: int, bits_per_sym: int,
-                pilot: Sequence[complex], combiner: int = RX_COMB_MRC, n_users: int = 1, pilot_spacing: int = 1):
+                pilot: Sequence[complex], combiner: int = RX_COMB_MRC, n_users: int = 1, pilot_spacing: int = 1,
+                fft_mode: int = RX_FFT_RADIX_F32):
     """Build an ``rx_params`` plus the float buffer its pilot pointer refers to (keep both alive)."""
     pil = np.ascontiguousarray(np.asarray(pilot, dtype=np.complex64)).view(np.float32)
     p = rx_params(n_ant, fft_len, cp_len, n_used, n_sym, bits_per_sym, combiner, n_users,
-                  pil.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), pilot_spacing)
+                  pil.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), pilot_spacing, fft_mode)
     return p, pil
 
 
@@ -258,20 +262,20 @@ class Plan:
 
     def __init__(self, n_ant: int, fft_len: int, cp_len: int, n_used: int, n_sym: int, bits_per_sym: int,
                  pilot: Sequence[complex], combiner: int = RX_COMB_MRC, n_users: int = 1,
-                 pilot_spacing: int = 1):
+                 pilot_spacing: int = 1, fft_mode: int = RX_FFT_RADIX_F32):
         self.n_ant, self.fft_len, self.cp_len, self.n_used = n_ant, fft_len, cp_len, n_used
         self.n_sym, self.bits_per_sym, self.combiner = n_sym, bits_per_sym, combiner
-        self.pilot_spacing = pilot_spacing
+        self.pilot_spacing, self.fft_mode = pilot_spacing, fft_mode
         self._params, self._pilot = make_params(n_ant, fft_len, cp_len, n_used, n_sym, bits_per_sym, pilot,
-                                                combiner, n_users, pilot_spacing)
+                                                combiner, n_users, pilot_spacing, fft_mode)
         st, self._plan = rx_plan_create(self._params)
         if st != RX_OK:
             raise RxError(st, "rx_plan_create")
 
     @classmethod
-    def from_config(cls, cfg, pilot, combiner: int = RX_COMB_MRC) -> "Plan":
+    def from_config(cls, cfg, pilot, combiner: int = RX_COMB_MRC, fft_mode: int = RX_FFT_RADIX_F32) -> "Plan":
         return cls(cfg.n_ant, cfg.fft_len, cfg.cp_len, cfg.n_used, cfg.n_sym, cfg.bits_per_sym, pilot, combiner,
-                   pilot_spacing=getattr(cfg, "pilot_spacing", 1))
+                   pilot_spacing=getattr(cfg, "pilot_spacing", 1), fft_mode=fft_mode)
 
     def close(self):
         if getattr(self, "_plan", None):

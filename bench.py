@@ -361,20 +361,90 @@ def bench_sync(args):
     print(json.dumps(rec), flush=True)
 
 
+def bench_precision(args):
+    """The 128-antenna, N=2048, 64-QAM shape with the FFT in each arithmetic:
+    FP32 radix (vector units) and the DFT-stage GEMMs on fp16 / bf16 MFMA,
+    with and without the hi+lo split.  Per mode: throughput over `--slots`
+    resident slots, the FFT's RMS error against an FP64 FFT (numpy) of the same
+    int16 symbols, and EVM and BER at 10, 20 and 30 dB."""
+    import numpy as np
+    from rxgen import C4, make_frames
+    workers = args.workers if args.workers > 0 else min(16, os.cpu_count() or 1)
+    S = args.slots
+    t0 = time.time()
+    fr = make_frames(C4, n_slots=S, workers=workers)
+    qual = {snr: make_frames(C4.replace(name=f"c4_{snr:g}dB", snr_db=(snr, snr), seed=C4.seed + int(snr)),
+                             n_slots=args.quality_slots, workers=workers) for snr in (10.0, 20.0, 30.0)}
+    log(f"generated {S} slots of {C4.name} ({fr.iq.nbytes / 1e6:.1f} MB) and quality sets in {time.time() - t0:.1f} s")
+    import torch
+    from paper_1901_07499_amd import rx
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    A, N, CP, T, U, B = C4.n_ant, C4.fft_len, C4.cp_len, C4.n_sym, C4.n_used, C4.bits_per_sym
+    iq = torch.from_numpy(fr.iq).to(dev)
+    # FP64 reference spectrum of the first slot's symbols (numpy, not the receiver's oracle)
+    x = fr.iq[0].astype(np.float64)
+    ref = np.fft.fft(x[..., CP:, 0] + 1j * x[..., CP:, 1], axis=-1)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = {}
+    for name, code in rx.FFT_MODES.items():
+        plan = rx.Plan.from_config(C4, fr.pilot, fft_mode=code)
+        bufs = (torch.empty((S, A, U, 2), dtype=torch.float32, device=dev), None,
+                torch.empty((S, T - 1, U * B // 8), dtype=torch.uint8, device=dev))
+        for _ in range(args.warmup):
+            plan.process(iq, out=bufs)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            plan.process(iq, out=bufs)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        Y = plan.debug_fft(iq[:1]).cpu().numpy()
+        Y = Y[0, ..., 0].astype(np.float64) + 1j * Y[0, ..., 1]
+        fft_err = float(np.sqrt(np.mean(np.abs(Y - ref) ** 2) / np.mean(np.abs(ref) ** 2)))
+        q = {}
+        for snr, f in qual.items():
+            qp = rx.Plan.from_config(f.cfg, f.pilot, fft_mode=code)
+            _, xh, bits = qp.process(torch.from_numpy(f.iq).to(dev))
+            xh = xh.cpu().numpy()
+            xc = xh[..., 0].astype(np.float64) + 1j * xh[..., 1]
+            evm = float(np.sqrt(np.mean(np.abs(xc - f.X) ** 2) / np.mean(np.abs(f.X) ** 2)))
+            sent = np.unpackbits(f.packed_bits(), axis=-1)
+            errs = int(np.count_nonzero(np.unpackbits(bits.cpu().numpy(), axis=-1) != sent))
+            q[f"{snr:g}dB"] = {"evm_rms": round(evm, 6), "ber": errs / sent.size, "bit_errors": errs}
+        samples = S * T * A * (N + CP)
+        out[name] = {"ms_per_step": round(ms, 5), "antenna_samples_per_s": samples / (ms * 1e-3),
+                     "fft_rms_rel_error_vs_fp64": fft_err, "quality": q}
+        log(f"{name}: {ms:.4f} ms, FFT error {fft_err:.3e}, {q}")
+    best = out["f16_split"]
+    rec = {"metric": "antenna-samples/s through FFT+LS+demod with the FFT as fp16/bf16 MFMA DFT GEMMs; "
+                     "FFT error, EVM, BER per mode", "value": best["antenna_samples_per_s"],
+           "unit": "antenna-samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": best["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f16 MFMA with hi+lo split, f32 accumulate", "data": "synthetic",
+           "config": {"workload": C4.name, "n_ant": A, "fft_len": N, "cp_len": CP, "n_used": U, "n_sym": T,
+                      "bits_per_sym": B, "n_slots": S, "quality_slots": args.quality_slots},
+           "modes": out, "kernel_hash": kernel_hash()}
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4", "batch", "denoiser", "sync"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4", "batch", "denoiser", "sync", "precision"])
     ap.add_argument("--frames", type=int, default=256, help="frames of the batch workload")
-    ap.add_argument("--slots", type=int, default=32, help="slots of the denoiser and sync workloads")
-    ap.add_argument("--quality-slots", type=int, default=8, help="slots per SNR of the denoiser quality figures")
+    ap.add_argument("--slots", type=int, default=32, help="slots of the denoiser, sync and precision workloads")
+    ap.add_argument("--quality-slots", type=int, default=8,
+                    help="slots per SNR of the denoiser and precision quality figures")
     ap.add_argument("--dn-steps", type=int, default=2000, help="training steps of the denoiser workload")
     ap.add_argument("--dn-rows", type=int, default=256, help="rows (antenna estimates) per training step")
     ap.add_argument("--dn-lr", type=float, default=2e-3, help="Adam learning rate")
     ap.add_argument("--workers", type=int, default=0,
-                    help="generator processes for the denoiser workload (0 = up to 16; 1 under a profiler)")
+                    help="generator processes for the denoiser and precision workloads (0 = up to 16; "
+                         "1 under a profiler)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-quality", action="store_true", help="skip the 20 dB quality figures")
     ap.add_argument("--gen-unique", type=int, default=0,
@@ -404,6 +474,9 @@ def main():
         return
     if args.workload == "sync":
         bench_sync(args)
+        return
+    if args.workload == "precision":
+        bench_precision(args)
         return
     from rxgen import C1, C2, C2_20DB, C4, make_frames
     cfg = {"c1": C1, "c2": C2, "c4": C4}[args.workload]

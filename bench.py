@@ -432,8 +432,9 @@ def bench_precision(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    # about 50 ms of untimed work first: the GPU's clocks settle within ~100 steps
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4", "batch", "denoiser", "sync", "precision"])
     ap.add_argument("--frames", type=int, default=256, help="frames of the batch workload")
     ap.add_argument("--slots", type=int, default=32, help="slots of the denoiser, sync and precision workloads")

@@ -32,12 +32,14 @@
 //
 // Backward (dn_backward_kernel): same tiling, transposed convolutions
 // g_{l-1}[ci][p] = sum_{co,k} W_l[co][ci][k] d_l[co][p+3-k], masked by
-// x_{l-1} > 0, give d3, d2, d1.
+// x_{l-1} > 0, give d3, d2, d1.  The masks come as one 32-bit word per
+// position and layer, written by the training forward from LDS.
 //
 // Weight gradients (dn_wgrad_kernel): dW_l[co][ci][k] = sum_{r,p} d_l[co][p]
-// x_{l-1}[ci][p+k-3], a GEMM with K = positions; each workgroup reduces its
-// own rows into a partial vector, and dn_reduce_kernel sums the partials in
-// a fixed order (deterministic) and applies Adam (Kingma and Ba, 2015).
+// x_{l-1}[ci][p+k-3], a GEMM with K = positions; workgroup (x, y) reduces
+// rows range x of layer y into partial vector x, and dn_reduce_kernel sums
+// the partials in a fixed order (deterministic) and applies Adam (Kingma and
+// Ba, 2015).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -140,6 +142,30 @@ __device__ __forceinline__ void store_global(bfbits* __restrict__ G, int64_t UP,
     for (int i = 0; i < 4; i++) G[(int64_t)(16 * h + 4 * q + i) * UP + p] = (bfbits)bf16_bits(v[h][i]);
 }
 
+// ReLU mask words of the tile's own positions [t0, t0 + TO) of a layer just
+// written to X (LDS index of position p is p - t0 + 12): bit c of
+// Mg[p] = (x[c][p] > 0).  One thread per position.
+__device__ __forceinline__ void store_masks(const bfbits* __restrict__ X, int t0, int U, uint32_t* __restrict__ Mg) {
+  const int i = threadIdx.x;
+  const int p = t0 + i;
+  if (i < TO && p < U) {
+    const uint4* row = reinterpret_cast<const uint4*>(X + (i + BASE_F) * RS);
+    uint32_t m = 0;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const uint4 v = row[k];
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const uint32_t lo = w[j] & 0xFFFFu, hi = w[j] >> 16;
+        m |= (uint32_t)((lo & 0x8000u) == 0 && lo != 0) << (8 * k + 2 * j);
+        m |= (uint32_t)((hi & 0x8000u) == 0 && hi != 0) << (8 * k + 2 * j + 1);
+      }
+    }
+    Mg[p] = m;
+  }
+}
+
 __device__ __forceinline__ void bias_init(f32x4 (&acc)[2], const float* __restrict__ b) {
   const int q = (threadIdx.x & 63) >> 4;
 #pragma unroll
@@ -238,6 +264,7 @@ __global__ __launch_bounds__(kBlock) void dn_forward_kernel(const float2* __rest
         if (TRAIN && in && p >= t0 && p < t0 + TO) store_global(io.X1 + row * 32 * UP, UP, p, acc);
       }
       __syncthreads();
+      if (TRAIN) store_masks(XA, t0, U, io.M1 + row * UP);
       // layer 2: A -> B
       for (int u = wave; u < U2; u += 4) {
         const int idx = 6 + 16 * u + r;
@@ -254,6 +281,7 @@ __global__ __launch_bounds__(kBlock) void dn_forward_kernel(const float2* __rest
         if (TRAIN && in && p >= t0 && p < t0 + TO) store_global(io.X2 + row * 32 * UP, UP, p, acc);
       }
       __syncthreads();
+      if (TRAIN) store_masks(XB, t0, U, io.M2 + row * UP);
       // layer 3: B -> A
       for (int u = wave; u < U3; u += 4) {
         const int idx = 9 + 16 * u + r;
@@ -270,6 +298,7 @@ __global__ __launch_bounds__(kBlock) void dn_forward_kernel(const float2* __rest
         if (TRAIN && in && p >= t0 && p < t0 + TO) store_global(io.X3 + row * 32 * UP, UP, p, acc);
       }
       __syncthreads();
+      if (TRAIN) store_masks(XA, t0, U, io.M3 + row * UP);
       // layer 4: A -> output (MFMA rows 0, 1 are the real and imaginary parts)
       for (int u = wave; u < U4; u += 4) {
         const int p = t0 + 16 * u + r;
@@ -314,14 +343,14 @@ __global__ __launch_bounds__(kBlock) void dn_forward_kernel(const float2* __rest
 //   g1   computed for t0   + [0, 240) (15 units) -> d1 = g1 [x1 > 0]
 // The transposed layer 4 has K = 32 slots (tap 3+4q-j/2, channel j%2) of which
 // taps 0..6 are real: lane quarter q reads d4 at p-4q .. p-4q+3.
-__device__ __forceinline__ void mask_unit(f32x4 (&acc)[2], const bfbits* __restrict__ Xg, int64_t UP, int p,
-                                          bool in) {
+__device__ __forceinline__ void mask_unit(f32x4 (&acc)[2], const uint32_t* __restrict__ Mg, int p, bool in) {
   const int q = (threadIdx.x & 63) >> 4;
+  const uint32_t m = in ? Mg[p] : 0u;
 #pragma unroll
   for (int h = 0; h < 2; h++)
 #pragma unroll
     for (int i = 0; i < 4; i++) {
-      const bool on = in && bf16_float(Xg[(int64_t)(16 * h + 4 * q + i) * UP + p]) > 0.f;
+      const bool on = (m >> (16 * h + 4 * q + i)) & 1u;
       // round to bf16 here: the delta enters the next products and the
       // weight gradient as bf16
       acc[h][i] = on ? bf16_float(bf16_bits(acc[h][i])) : 0.f;
@@ -366,7 +395,7 @@ __global__ __launch_bounds__(kBlock) void dn_backward_kernel(int64_t rows, int U
         acc[0] = mfma(g4[0], bv, acc[0]);
         acc[1] = mfma(g4[1], bv, acc[1]);
         const bool in = p >= 0 && p < U;
-        mask_unit(acc, io.X3 + row * 32 * UP, UP, p, in);
+        mask_unit(acc, io.M3 + row * UP, p, in);
         store_unit(DA, idx, acc);
         if (in && p >= t0 && p < t0 + TO) store_global(io.D3 + row * 32 * UP, UP, p, acc);
       }
@@ -378,7 +407,7 @@ __global__ __launch_bounds__(kBlock) void dn_backward_kernel(int64_t rows, int U
         f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
         unit32<-1>(DA, 15 + 16 * u + 3, g3, acc);
         const bool in = p >= 0 && p < U;
-        mask_unit(acc, io.X2 + row * 32 * UP, UP, p, in);
+        mask_unit(acc, io.M2 + row * UP, p, in);
         store_unit(DB, idx, acc);
         if (in && p >= t0 && p < t0 + TO) store_global(io.D2 + row * 32 * UP, UP, p, acc);
       }
@@ -389,7 +418,7 @@ __global__ __launch_bounds__(kBlock) void dn_backward_kernel(int64_t rows, int U
         f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
         unit32<-1>(DB, 18 + 16 * u + 3, g2, acc);
         const bool in = p < U;
-        mask_unit(acc, io.X1 + row * 32 * UP, UP, p, in);
+        mask_unit(acc, io.M1 + row * UP, p, in);
         if (in) store_global(io.D1 + row * 32 * UP, UP, p, acc);
       }
     }
@@ -536,24 +565,46 @@ __global__ __launch_bounds__(kBlock) void dn_wgrad_kernel(int64_t rows, int U, D
   const int64_t r0 = rows * blockIdx.x / G, r1 = rows * (blockIdx.x + 1) / G;
   float* part = io.part + (int64_t)blockIdx.x * kParams;
   const int64_t UP = io.UP;
-  wgrad_layer<2, 32>(io.D1, io.X0, UP, U, r0, r1, dT, xT, part + kPW1, part + kPB1);
-  wgrad_layer<32, 32>(io.D2, io.X1, UP, U, r0, r1, dT, xT, part + kPW2, part + kPB2);
-  wgrad_layer<32, 32>(io.D3, io.X2, UP, U, r0, r1, dT, xT, part + kPW3, part + kPB3);
-  wgrad_layer<32, 2>(io.D4, io.X3, UP, U, r0, r1, dT, xT, part + kPW4, part + kPB4);
+  // one layer per workgroup (grid y): each parameter of partial vector
+  // blockIdx.x is written by exactly one workgroup
+  switch (blockIdx.y) {
+    case 0: wgrad_layer<2, 32>(io.D1, io.X0, UP, U, r0, r1, dT, xT, part + kPW1, part + kPB1); break;
+    case 1: wgrad_layer<32, 32>(io.D2, io.X1, UP, U, r0, r1, dT, xT, part + kPW2, part + kPB2); break;
+    case 2: wgrad_layer<32, 32>(io.D3, io.X2, UP, U, r0, r1, dT, xT, part + kPW3, part + kPB3); break;
+    default: wgrad_layer<32, 2>(io.D4, io.X3, UP, U, r0, r1, dT, xT, part + kPW4, part + kPB4); break;
+  }
 }
 
 // ------------------------------------------------------------------ reduce + Adam
-// grad[i] = sum over workgroups g (in order) of part[g][i]; optionally the
-// Adam update of theta, m, v (bias corrections c1 = 1/(1-beta1^t),
-// c2 = 1/(1-beta2^t) from the host).  Block 0 also sums the loss partials.
+// grad[i] = sum over workgroup partials g of part[g][i]: a block owns 64
+// parameters; its 4 wavefronts sum the partials g = w, w + 4, ... (in order,
+// coalesced over the 64 parameters), then wavefront 0 adds the 4 sums in
+// order, so the result is deterministic.  Optionally the Adam update of theta,
+// m, v (bias corrections c1 = 1/(1-beta1^t), c2 = 1/(1-beta2^t) from the
+// host).  Block 0 also sums the loss partials.
+constexpr int kRedParams = 64;
+
 __global__ __launch_bounds__(kBlock) void dn_reduce_kernel(const float* __restrict__ part, int n_part,
                                                            const float* __restrict__ loss_part, int n_loss,
                                                            float* __restrict__ grad, float* __restrict__ loss,
                                                            AdamArgs adam) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+  __shared__ float sums[4][kRedParams];
+  const int j = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = blockIdx.x * kRedParams + j;
+  float acc = 0.f;
   if (i < kParams) {
-    float g = 0.f;
-    for (int b = 0; b < n_part; b++) g += part[(int64_t)b * kParams + i];
+    int b = w;
+    for (; b + 12 < n_part; b += 16) {  // four independent loads in flight
+      const float v0 = part[(int64_t)b * kParams + i], v1 = part[(int64_t)(b + 4) * kParams + i];
+      const float v2 = part[(int64_t)(b + 8) * kParams + i], v3 = part[(int64_t)(b + 12) * kParams + i];
+      acc = (((acc + v0) + v1) + v2) + v3;
+    }
+    for (; b < n_part; b += 4) acc += part[(int64_t)b * kParams + i];
+  }
+  sums[w][j] = acc;
+  __syncthreads();
+  if (w == 0 && i < kParams) {
+    const float g = ((sums[0][j] + sums[1][j]) + sums[2][j]) + sums[3][j];
     if (grad) grad[i] = g;
     if (adam.theta) {
       const float m = adam.beta1 * adam.m[i] + (1.0f - adam.beta1) * g;
@@ -752,9 +803,9 @@ hipError_t dn_train(const float2* Hin, const float2* Htrue, int64_t rows, int U,
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(dn::dn_backward_kernel, dim3(G), dim3(dn::kBlock), bwd_lds(), st, rows, U, fr, io);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(dn::dn_wgrad_kernel, dim3(G), dim3(dn::kBlock), 0, st, rows, U, io);
+  hipLaunchKernelGGL(dn::dn_wgrad_kernel, dim3(G, 4), dim3(dn::kBlock), 0, st, rows, U, io);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(dn::dn_reduce_kernel, dim3((kParams + dn::kBlock - 1) / dn::kBlock), dim3(dn::kBlock), 0, st,
+  hipLaunchKernelGGL(dn::dn_reduce_kernel, dim3((kParams + dn::kRedParams - 1) / dn::kRedParams), dim3(dn::kBlock), 0, st,
                      (const float*)io.part, G, (const float*)io.loss_part, G, grad, loss, adam);
   return hipGetLastError();
 }

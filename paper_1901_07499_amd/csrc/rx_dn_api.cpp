@@ -36,7 +36,7 @@ int check_dn(rx_dn_t dn) {
 // Workspace carve-up for `rows` rows.
 struct Carve {
   int64_t UP = 0;
-  size_t off[10] = {0};  // X0 X1 X2 X3 D1 D2 D3 D4 part loss_part
+  size_t off[13] = {0};  // X0 X1 X2 X3 D1 D2 D3 D4 part loss_part M1 M2 M3
   size_t total = 0;
 };
 
@@ -44,10 +44,12 @@ Carve carve(int U, int64_t rows) {
   Carve c;
   c.UP = round_up(U, 8);
   const size_t two = (size_t)rows * 2 * c.UP * 2, wide = (size_t)rows * 32 * c.UP * 2;
-  const size_t sizes[10] = {two, wide, wide, wide, wide, wide, wide, two,
-                            (size_t)rx::dn_grid(rows) * rx::kParams * 4, (size_t)rx::dn_grid(rows) * 4};
+  const size_t mask = (size_t)rows * c.UP * 4;
+  const size_t sizes[13] = {two, wide, wide, wide, wide, wide, wide, two,
+                            (size_t)rx::dn_grid(rows) * rx::kParams * 4, (size_t)rx::dn_grid(rows) * 4,
+                            mask, mask, mask};
   size_t o = 0;
-  for (int i = 0; i < 10; i++) {
+  for (int i = 0; i < 13; i++) {
     c.off[i] = o;
     o += (size_t)round_up((int64_t)sizes[i], 256);
   }
@@ -136,6 +138,9 @@ static int train_common(rx_dn_t dn, const float* H_in, const float* H_true, int6
   for (int i = 0; i < 8; i++) *bufs[i] = reinterpret_cast<uint16_t*>(w + c.off[i]);
   io.part = reinterpret_cast<float*>(w + c.off[8]);
   io.loss_part = reinterpret_cast<float*>(w + c.off[9]);
+  io.M1 = reinterpret_cast<uint32_t*>(w + c.off[10]);
+  io.M2 = reinterpret_cast<uint32_t*>(w + c.off[11]);
+  io.M3 = reinterpret_cast<uint32_t*>(w + c.off[12]);
   const hipError_t e = rx::dn_train(reinterpret_cast<const float2*>(H_in), reinterpret_cast<const float2*>(H_true),
                                     rows, dn->U, dn->frag, dn->theta, io, grad, loss, adam, s);
   return e == hipSuccess ? RX_OK : RX_E_HIP;

@@ -82,6 +82,7 @@ struct DnTrainIo {
   float inv_count;  // 1 / (rows * U)
   uint16_t *X0, *X1, *X2, *X3;  // x0 (2 channels), x1..x3 (32)
   uint16_t *D1, *D2, *D3, *D4;  // deltas: d1..d3 (32 channels), d4 (2)
+  uint32_t *M1, *M2, *M3;       // ReLU masks of x1..x3: [row][UP], bit c = (x[c] > 0)
   float* part;       // [grid][kParams] weight-gradient partials
   float* loss_part;  // [grid]
 };

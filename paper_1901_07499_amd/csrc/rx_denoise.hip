@@ -26,7 +26,10 @@
 // the 16-byte operand reads of 8 consecutive positions conflict-free).  A
 // GEMM unit is 16 positions x 32 output channels (two MFMA rows of 16); the
 // K dimension is (tap, input channel): one 16-byte LDS read per tap.  The
-// weights of all four layers stay in registers for the workgroup's life.
+// last layer (2 output channels) puts its 7 taps into the MFMA rows instead
+// (14 of 16 rows used, one MFMA per 16 positions) and sums the taps over
+// positions from LDS.  The weights of all four layers stay in registers for
+// the workgroup's life.
 // Training stores x0..x3 and the output delta d4 = 2 (x0 + a_4 - t) / (R U)
 // channel-major in global memory, plus a per-workgroup loss partial.
 //
@@ -60,7 +63,9 @@ constexpr int RS = 40;     // bf16 per LDS position row (32 channels + 8 pad)
 constexpr int BASE_F = 12; // forward: LDS index of position t0
 constexpr int BASE_B = 18; // backward: LDS index of position t0
 // GEMM units (16 positions) per layer and tile; see the halo layout below.
-constexpr int U1 = 17, U2 = 16, U3 = 16, U4 = 15;
+constexpr int U1 = 17, U2 = 16, U3 = 16, U4P = 16;
+constexpr int PS = 260;  // LDS row pitch (floats) of the folded last layer's per-tap outputs
+static_assert(14 * PS * 4 <= NPOS * RS * 2, "per-tap outputs fit in one activation buffer");
 constexpr int BU3 = 16, BU2 = 16, BU1 = 15;
 
 __device__ __forceinline__ f32x4 mfma(const bf16x8& a, const bf16x8& b, const f32x4& c) {
@@ -181,7 +186,8 @@ __device__ __forceinline__ void bias_init(f32x4 (&acc)[2], const float* __restri
 //   x1  computed for t0-9  + [0, 272)  (17 units)   -> buffer A
 //   x2  computed for t0-6  + [0, 256)  (16 units)   -> buffer B
 //   x3  computed for t0-3  + [0, 256)  (16 units)   -> buffer A
-//   out computed for t0    + [0, 240)  (15 units)
+//   P   layer 4 per tap, for t0-3 + [0, 256) (16 units) -> buffer B (float)
+//   out summed for t0 + [0, 240) from P at p-3..p+3
 // Layer l's output at p needs x_{l-1} at p-3..p+3; each range above covers
 // what the next layer needs for the final 240 outputs (layer 3 also reads up
 // to 6 stale positions past x2's range; they reach only discarded outputs).
@@ -199,7 +205,7 @@ __global__ __launch_bounds__(kBlock) void dn_forward_kernel(const float2* __rest
   __shared__ float red[4];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r = lane & 15, q = lane >> 4;
 
-  bf16x8 w1[2], w2[2][7], w3[2][7], w4[7];
+  bf16x8 w1[2], w2[2][7], w3[2][7], w4;
 #pragma unroll
   for (int h = 0; h < 2; h++) {
     w1[h] = frag[kF1 + h * 64 + lane];
@@ -209,8 +215,7 @@ __global__ __launch_bounds__(kBlock) void dn_forward_kernel(const float2* __rest
       w3[h][k] = frag[kF3 + (h * 7 + k) * 64 + lane];
     }
   }
-#pragma unroll
-  for (int k = 0; k < 7; k++) w4[k] = frag[kF4 + k * 64 + lane];
+  w4 = frag[kF4 + lane];
   const float* b1 = theta + kPB1;
   const float* b2 = theta + kPB2;
   const float* b3 = theta + kPB3;
@@ -299,32 +304,41 @@ __global__ __launch_bounds__(kBlock) void dn_forward_kernel(const float2* __rest
       }
       __syncthreads();
       if (TRAIN) store_masks(XA, t0, U, io.M3 + row * UP);
-      // layer 4: A -> output (MFMA rows 0, 1 are the real and imaginary parts)
-      for (int u = wave; u < U4; u += 4) {
-        const int p = t0 + 16 * u + r;
-        f32x4 acc;
+      // layer 4, taps folded into the MFMA rows: P[(co, k)][p] = sum_ci
+      // W4[co][ci][k] x3[ci][p] (rows co * 7 + k, 14 of 16 used) for positions
+      // t0 - 3 .. t0 + 252, kept in LDS as float [row][position] in buffer B
+      // (so the tap sums below read consecutive words)
+      float* Pb = reinterpret_cast<float*>(XB);
+      for (int u = wave; u < U4P; u += 4) {
+        const bf16x8 bv = as_bf16x8(*reinterpret_cast<const uint4*>(XA + (9 + 16 * u + r) * RS + 8 * q));
+        const f32x4 acc = mfma(w4, bv, f32x4{0.f, 0.f, 0.f, 0.f});
 #pragma unroll
-        for (int i = 0; i < 4; i++) acc[i] = (4 * q + i < 2) ? b4[4 * q + i] : 0.f;
+        for (int i = 0; i < 4; i++)
+          if (4 * q + i < 14) Pb[(4 * q + i) * PS + 16 * u + r] = acc[i];
+      }
+      __syncthreads();
+      // out[co][p] = b4[co] + sum_k P[(co, k)][p + k - 3]
+      for (int i = tid; i < TO; i += kBlock) {
+        const int p = t0 + i;
+        if (p >= U) break;
+        float o0 = b4[0], o1 = b4[1];
 #pragma unroll
         for (int k = 0; k < 7; k++) {
-          const bf16x8 bv =
-              as_bf16x8(*reinterpret_cast<const uint4*>(XA + (12 + 16 * u - 3 + k + r) * RS + 8 * q));
-          acc = mfma(w4[k], bv, acc);
+          o0 += Pb[k * PS + i + k];
+          o1 += Pb[(7 + k) * PS + i + k];
         }
-        if (q == 0 && p < U) {
-          const float2 h = hrow[p];
-          if (!TRAIN) {
-            Hout[row * U + p] = make_float2(fmaf(s, acc[0], h.x), fmaf(s, acc[1], h.y));
-          } else {
-            const float2 t = io.Htrue[row * U + p];
-            const float ex = h.x * inv + acc[0] - t.x * inv;
-            const float ey = h.y * inv + acc[1] - t.y * inv;
-            const bool live = s > 0.f;
-            if (live) loss = fmaf(ex, ex, fmaf(ey, ey, loss));
-            const float c = live ? 2.0f * io.inv_count : 0.f;
-            io.D4[(row * 2 + 0) * UP + p] = (bfbits)bf16_bits(c * ex);
-            io.D4[(row * 2 + 1) * UP + p] = (bfbits)bf16_bits(c * ey);
-          }
+        const float2 h = hrow[p];
+        if (!TRAIN) {
+          Hout[row * U + p] = make_float2(fmaf(s, o0, h.x), fmaf(s, o1, h.y));
+        } else {
+          const float2 t = io.Htrue[row * U + p];
+          const float ex = h.x * inv + o0 - t.x * inv;
+          const float ey = h.y * inv + o1 - t.y * inv;
+          const bool live = s > 0.f;
+          if (live) loss = fmaf(ex, ex, fmaf(ey, ey, loss));
+          const float c = live ? 2.0f * io.inv_count : 0.f;
+          io.D4[(row * 2 + 0) * UP + p] = (bfbits)bf16_bits(c * ex);
+          io.D4[(row * 2 + 1) * UP + p] = (bfbits)bf16_bits(c * ey);
         }
       }
     }
@@ -640,11 +654,11 @@ __device__ __forceinline__ int frag_param(int e) {
     return (layer == 0 ? kPW2 : kPW3) + (co * 32 + ci) * 7 + k;
   }
   b -= 28;
-  if (b < 7) {  // F4[k]: row co = r (< 2), slot ci = 8q + j
-    const int k = b, co = r, ci = 8 * q + j;
-    return co < 2 ? kPW4 + (co * 32 + ci) * 7 + k : -1;
+  if (b < 1) {  // F4 (taps folded into rows): row r = co * 7 + k (< 14), slot ci = 8q + j
+    const int co = r / 7, k = r % 7, ci = 8 * q + j;
+    return r < 14 ? kPW4 + (co * 32 + ci) * 7 + k : -1;
   }
-  b -= 7;
+  b -= 1;
   if (b < 2) {  // G4[h]: row ci = 16h + r, slot (tap 3 + 4q - j/2, channel j%2)
     const int ci = 16 * b + r, tap = 3 + 4 * q - (j >> 1), co = j & 1;
     return tap <= 6 ? kPW4 + (co * 32 + ci) * 7 + tap : -1;

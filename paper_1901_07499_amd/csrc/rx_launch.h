@@ -70,9 +70,10 @@ constexpr int kParams = 15330;
 constexpr int kPW1 = 0, kPB1 = 448, kPW2 = 480, kPB2 = 7648, kPW3 = 7680, kPB3 = 14848, kPW4 = 14880,
               kPB4 = 15328;
 // bf16 MFMA operand fragments of the weights, in 16-byte units (64 per block):
-// forward F1[2], F2[2][7], F3[2][7], F4[7]; transposed G4[2], G3[2][7], G2[2][7].
-constexpr int kF1 = 0, kF2 = 128, kF3 = 1024, kF4 = 1920, kG4 = 2368, kG3 = 2496, kG2 = 3392,
-              kFragUnits = 4288;
+// forward F1[2], F2[2][7], F3[2][7], F4 (taps folded into rows); transposed
+// G4[2], G3[2][7], G2[2][7].
+constexpr int kF1 = 0, kF2 = 128, kF3 = 1024, kF4 = 1920, kG4 = 1984, kG3 = 2112, kG2 = 3008,
+              kFragUnits = 3904;
 
 // Training buffers (bf16 bits, channel-major [row][channel][UP], UP = U
 // rounded up to 8) and partial sums.

@@ -155,6 +155,37 @@ def test_forward_matches_oracle(rx, U, rows, seed):
     _check_forward(out, ref, hl)
 
 
+@pytest.mark.parametrize("U,rows", [(3, 4), (7, 1), (241, 3), (481, 2)])
+def test_forward_odd_lengths_and_tile_edges(rx, U, rows):
+    # arbitrary row lengths: one position past a 240-output tile, odd U, a single row
+    rng = np.random.default_rng(U)
+    h = rng.standard_normal((rows, U)) + 1j * rng.standard_normal((rows, U))
+    th = _params(U)
+    dn = rx.Denoiser(U)
+    dn.load(torch.from_numpy(th.astype(np.float32)).cuda())
+    out = as_complex(dn.apply(_cuda(h)))
+    torch.cuda.synchronize()
+    ref = odn.forward(th.astype(np.float32).astype(np.float64), h.astype(np.complex64).astype(np.complex128),
+                      bf16_ops=True)
+    _check_forward(out, ref, h)
+
+
+def test_gradient_single_row_odd_length(rx):
+    rng = np.random.default_rng(8)
+    U = 243
+    ht = rng.standard_normal((1, U)) + 1j * rng.standard_normal((1, U))
+    hl = ht + 0.3 * (rng.standard_normal((1, U)) + 1j * rng.standard_normal((1, U)))
+    th = _params(8, last_scale=0.3).astype(np.float32).astype(np.float64)
+    dn = rx.Denoiser(U)
+    dn.load(torch.from_numpy(th.astype(np.float32)).cuda())
+    loss, g = dn.grad(_cuda(hl), _cuda(ht))
+    torch.cuda.synchronize()
+    rl, rg = odn.loss_grad(th, hl.astype(np.complex64).astype(np.complex128),
+                           ht.astype(np.complex64).astype(np.complex128), bf16_ops=True)
+    assert abs(loss.item() - rl) <= 1e-4 * rl
+    assert _rel(g.cpu().numpy().astype(np.float64), rg) <= 2e-2
+
+
 def test_forward_in_place_zero_rows_and_identity(rx):
     U = 300
     _, hl = _rows(6, 9, n_used=U, fft_len=512, cp_len=37)

@@ -71,6 +71,21 @@ def test_split_f16_path_meets_the_fp32_parity_bar(rx):
     check_bits(bits.cpu().numpy(), ref.bits, ref.xhat, cfg.bits_per_sym)
 
 
+@pytest.mark.parametrize("A,S", [(5, 3), (1, 1), (130, 1)])
+def test_split_f16_path_ragged_antenna_counts(rx, A, S):
+    # antenna counts that leave wavefronts idle in the estimate and demod loops
+    cfg = C4.replace(n_ant=A, n_slots=S, n_sym=4)
+    fr = make_frames(cfg, n_slots=S)
+    print(f"[case] mfma path f16_split A={A} S={S}", flush=True)
+    plan = rx.Plan.from_config(cfg, fr.pilot, fft_mode=3)
+    H, xhat, bits = plan.process(torch.from_numpy(fr.iq).cuda(), want_H=True)
+    torch.cuda.synchronize()
+    ref = oracle.process_frame(fr.iq, fr.pilot, **_kw(cfg))
+    check_H(as_complex(H), ref.H)
+    check_xhat(as_complex(xhat), ref.xhat)
+    check_bits(bits.cpu().numpy(), ref.bits, ref.xhat, cfg.bits_per_sym)
+
+
 @pytest.mark.parametrize("mode", ["f16", "bf16", "bf16_split"])
 def test_path_error_follows_the_fft_error(rx, mode):
     code, bound = MODES[mode]

@@ -165,8 +165,9 @@ int rx_debug_fft(rx_plan_t plan, const int16_t* iq, int64_t n_slots, float* Y, v
  * The path per frame is the one of rx_process_frame (paper Sec. II-B and
  * II-C); the batch runs it for every frame in one graph launch.  Frames with
  * equal FFT length share one persistent estimate kernel and one persistent
- * demod kernel that take tiles from device work queues in frame order;
- * different FFT lengths run on independent graph branches.
+ * demod kernel that take tiles from device work queues (frames with more
+ * antennas first, ties in batch order); different FFT lengths run on
+ * independent graph branches.
  * ------------------------------------------------------------------------- */
 typedef struct rx_batch_s* rx_batch_t;
 

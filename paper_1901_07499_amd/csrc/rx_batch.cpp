@@ -91,7 +91,11 @@ int configure_class(rx_batch_s* b, BatchClass& c) {
   if (!rx::batch_kernels(c.N, c.max_u, c.demod_waves, c.est_jobs, c.dem, c.est)) return RX_E_UNSUPPORTED;
   std::vector<rx::FrameDesc> desc;
   std::vector<int> est_map, dem_map;
-  for (int i : c.frames) {
+  // Queue order: frames with more antennas (longer tiles) first, ties in batch
+  // order, so the last tiles of a class are short ones.
+  std::vector<int> order = c.frames;
+  std::stable_sort(order.begin(), order.end(), [b](int x, int y) { return b->p[x].n_ant > b->p[y].n_ant; });
+  for (int i : order) {
     const rx_params& p = b->p[i];
     rx::FrameDesc d;
     d.iq_off = b->iq_off[i] / 2;

@@ -1,14 +1,20 @@
 // rx_fft.hpp -- wavefront-level FFT building blocks for gfx950.
 //
-// An N-point FFT (N = 64 .. 2048) is computed by L = N / P lanes of one
-// 64-wide wavefront, each lane holding P complex points in VGPRs (P = 16, or
-// 32 for N = 2048); for N < 1024 one wavefront runs F = 64 / L transforms side
-// by side.  The transform is a self-sorting (Stockham) sequence of radix-R
+// An N-point FFT (N = 64 .. 2048) is computed by L = N / 16 lanes, each lane
+// holding P = 16 complex points in VGPRs.  For N < 1024 one 64-wide wavefront
+// runs F = 64 / L transforms side by side; N = 1024 fills one wavefront; N =
+// 2048 spans a pair of wavefronts of the workgroup (L = 128), which keeps the
+// per-lane state (and so the occupancy) of the N = 1024 transform.  Lane li of
+// a transform is thread li of its L-thread group: li = tid % L, transform slot
+// tid / L.  The transform is a self-sorting (Stockham) sequence of radix-R
 // passes: each lane applies R-point DFTs to R of its points held in registers,
-// and consecutive passes exchange data through a private, padded LDS region of
-// the wavefront.  No workgroup barrier is involved: a wavefront's LDS
+// and consecutive passes exchange data through a padded LDS region private to
+// the transform.  Within one wavefront no barrier is needed: its LDS
 // operations execute in program order, so a wavefront-scope fence (a pure
-// compiler ordering point) separates the reads and writes of each pass.
+// compiler ordering point) separates the reads and writes of each pass.  A
+// two-wavefront transform separates them with a workgroup barrier taken once
+// the wavefront's own LDS operations are complete; its outstanding global
+// loads (the next symbol's samples) stay in flight across it.
 //
 // Pass with radix R after stride NS (product of the earlier radices):
 // butterfly j in [0, N/R) takes x[j + r*N/R], r = 0..R-1, multiplies element r
@@ -154,14 +160,35 @@ __device__ __forceinline__ void wave_fence() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Workgroup barrier for LDS data only: waits for this wavefront's LDS
+// operations (lgkmcnt = 0, the gfx9 s_waitcnt encoding with vmcnt and expcnt
+// left at their maxima) and not for its global loads.  Every wavefront of the
+// workgroup must reach it the same number of times.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_s_waitcnt(0xc07f);
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ------------------------------------------------------------ pass schedule per N
 template <int N>
 struct FftShape {
-  static constexpr int P = (N >= 2048) ? 32 : 16;  // points per lane
-  static constexpr int L = N / P;                  // lanes per transform
-  static constexpr int F = 64 / L;                 // transforms per wavefront
+  static constexpr int P = 16;                      // points per lane
+  static constexpr int L = N / P;                   // lanes per transform
+  static constexpr int F = L < 64 ? 64 / L : 1;     // transforms per wavefront
+  static constexpr int WPT = L > 64 ? L / 64 : 1;   // wavefronts per transform
   static_assert(N >= 64 && N <= 2048 && (N & (N - 1)) == 0, "N must be a power of two in [64, 2048]");
 };
+
+// Separation of two passes' LDS accesses (see the top of this file).  With
+// WPT > 1 it is a workgroup barrier: code that calls it must be reached by
+// every wavefront of the workgroup equally often.
+template <int N>
+__device__ __forceinline__ void exchange_fence() {
+  if constexpr (FftShape<N>::WPT == 1) wave_fence();
+  else lds_barrier();
+}
 
 // Radix schedule per N: the first pass is always radix 16 (16 points of one
 // transform per lane, loaded straight from memory); later radices are chosen
@@ -272,7 +299,10 @@ __device__ __forceinline__ void stockham_pass(float2 (&v)[C][FftShape<N>::P], fl
           const int k = L * m + r * (N / R);
           v[c][m * R + r] = buf[c][(k % 16 == 0) ? pli + k + k / 16 : pad(li + k)];
         }
-    wave_fence();  // every lane's reads happen before any lane's writes
+    // every lane's reads happen before any lane's writes; the last pass writes
+    // nothing, and a two-wavefront transform skips that (barrier) fence: the
+    // caller fences before the buffer is written again
+    if constexpr (!LAST || FftShape<N>::WPT == 1) exchange_fence<N>();
   }
 #pragma unroll
   for (int c = 0; c < C; c++)
@@ -295,7 +325,7 @@ __device__ __forceinline__ void stockham_pass(float2 (&v)[C][FftShape<N>::P], fl
         }
       }
     }
-  if constexpr (!LAST) wave_fence();
+  if constexpr (!LAST) exchange_fence<N>();
 }
 
 // Whole transform of C symbols.  Inputs in v (first-pass order).  On return

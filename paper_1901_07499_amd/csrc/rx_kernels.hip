@@ -78,19 +78,32 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t n) {
 }
 
 // ------------------------------------------------------------------ estimate
-// LS estimate of one slot's antennas a_first, a_first + W*F, ... (J jobs of F
-// antennas per wavefront), the next job's samples requested before the
-// current transform.  slot_iq: the slot's samples [T][A][CP+N]; Hs: its
-// estimate [A][U].  No workgroup barrier inside.
+// Transforms a workgroup of W wavefronts runs side by side.
+template <int N, int W>
+constexpr int transforms_per_group() {
+  static_assert((64 * W) % FftShape<N>::L == 0, "a workgroup must hold whole transforms");
+  return 64 * W / FftShape<N>::L;
+}
+
+// LS estimate of one slot's antennas a_wg .. a_wg + TPW*J - 1: transform slot
+// ts = tid / L of the workgroup takes antennas a_wg + ts + j*TPW, j < J, the
+// next job's samples requested before the current transform.  slot_iq: the
+// slot's samples [T][A][CP+N]; Hs: its estimate [A][U].  The loop bound is
+// uniform over whoever shares an exchange fence (the wavefront, or the
+// workgroup for two-wavefront transforms): a transform whose antenna is past
+// A transforms a valid antenna's samples and stores nothing.
 template <int N, int W, int J>
 __device__ __forceinline__ void estimate_tile(const uint32_t* __restrict__ slot_iq, int A, int CP, int U,
                                               const float2* __restrict__ pf, float2* __restrict__ Hs,
-                                              int a_first, float2* lds, const FftTwiddles<N>& twr, int ps) {
+                                              int a_wg, float2* lds, const FftTwiddles<N>& twr, int ps) {
   using Sh = FftShape<N>;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int f = lane / Sh::L, li = lane % Sh::L;
-  const int a_step = W * Sh::F;
-  if (a_first >= A) return;
+  constexpr int TPW = transforms_per_group<N, W>();
+  const int li = threadIdx.x % Sh::L, ts = threadIdx.x / Sh::L;
+  const int f = ts % Sh::F;
+  // antenna whose validity ends the loop: the wavefront's first, or the
+  // workgroup's first when a transform spans wavefronts
+  const int a_lead = Sh::WPT > 1 ? a_wg : a_wg + ts - f;
+  if (a_lead >= A) return;
   // subcarrier of each spectrum register (clamped for the pilot-factor load;
   // unused bins are never stored) and its pilot factor
   int dq[Sh::P];
@@ -101,23 +114,20 @@ __device__ __forceinline__ void estimate_tile(const uint32_t* __restrict__ slot_
     pq[q] = pf[dq[q] >= 0 ? dq[q] : 0];
   }
   const uint32_t* pilot_sym = slot_iq + CP;  // symbol 0
-  auto rec_of = [&](int aj) {
-    const int a = aj + f;
-    return pilot_sym + (int64_t)(a < A ? a : aj) * (N + CP);
-  };
-  float2* buf = lds + (wave * Sh::F + f) * Lds<N>::kSlot;
+  // record of antenna a, or of the (valid) lead antenna lead when a >= A
+  auto rec_of = [&](int a, int lead) { return pilot_sym + (int64_t)(a < A ? a : lead) * (N + CP); };
+  float2* buf = lds + ts * Lds<N>::kSlot;
   uint32_t nxt[Sh::P];
-  load_symbol<N>(nxt, rec_of(a_first), li, a_first + f < A);
+  load_symbol<N>(nxt, rec_of(a_wg + ts, a_lead), li, a_wg + ts < A);
 #pragma unroll 1
   for (int j = 0; j < J; j++) {
-    const int a0 = a_first + j * a_step;
-    if (a0 >= A) break;
+    const int lead = a_lead + j * TPW;
+    if (lead >= A) break;
+    const int a = a_wg + ts + j * TPW;
     float2 v[Sh::P];
     unpack_symbol<N>(v, nxt);
-    const int an = a0 + a_step;
-    if (j + 1 < J && an < A) load_symbol<N>(nxt, rec_of(an), li, an + f < A);
+    if (j + 1 < J && lead + TPW < A) load_symbol<N>(nxt, rec_of(a + TPW, lead + TPW), li, a + TPW < A);
     fft_in_regs<N>(v, buf, li, twr);
-    const int a = a0 + f;
     if (ps <= 1) {
       if (a < A) {
         float2* hrow = Hs + (int64_t)a * U;
@@ -128,17 +138,17 @@ __device__ __forceinline__ void estimate_tile(const uint32_t* __restrict__ slot_
     } else {
       // comb: LS on the pilot subcarriers into this transform's LDS slot
       // (the FFT's last LDS reads are behind), then every subcarrier
-      wave_fence();
+      exchange_fence<N>();
 #pragma unroll
       for (int q = 0; q < Sh::P; q++)
         if (dq[q] >= 0 && dq[q] % ps == 0) buf[dq[q] / ps] = cmul(v[Spectrum<N>::reg(q)], pq[q]);
-      wave_fence();
+      exchange_fence<N>();
       if (a < A) {
         float2* hrow = Hs + (int64_t)a * U;
         for (int d = li; d < U; d += Sh::L) hrow[d] = comb_value(buf, d, U, ps);
       }
     }
-    wave_fence();  // this job's LDS reads precede the next job's writes
+    exchange_fence<N>();  // this job's LDS reads precede the next job's writes
   }
 }
 
@@ -150,7 +160,7 @@ __device__ __forceinline__ void tile_setup(FftTwiddles<N>& twr, float2* twtab, c
     FftTwiddles<N>::P3Lds::fill(twtab, tw, threadIdx.x, blockDim.x);
     __syncthreads();
   }
-  twr.load(tw, (threadIdx.x & 63) % FftShape<N>::L, twtab);
+  twr.load(tw, threadIdx.x % FftShape<N>::L, twtab);
 }
 
 // Uniform slots: workgroup = (slot, group of W*F*J antennas).
@@ -165,9 +175,9 @@ __global__ __launch_bounds__(64 * W) void estimate_kernel(const uint32_t* __rest
   tile_setup<N>(twr, twtab, tw);
   const int64_t s = blockIdx.x / blocks_per_slot;
   const int blk = blockIdx.x % blocks_per_slot;
-  const int a_first = blk * (W * FftShape<N>::F * J) + (threadIdx.x >> 6) * FftShape<N>::F;
-  estimate_tile<N, W, J>(iq + s * T * (int64_t)A * (N + CP), A, CP, U, pf, H + s * A * (int64_t)U, a_first, lds,
-                         twr, ps);
+  const int a_wg = blk * (transforms_per_group<N, W>() * J);
+  estimate_tile<N, W, J>(iq + s * T * (int64_t)A * (N + CP), A, CP, U, pf, H + s * A * (int64_t)U, a_wg, lds, twr,
+                         ps);
 }
 
 // ------------------------------------------------------------------ demod
@@ -190,8 +200,11 @@ __device__ __forceinline__ void demod_tile(const SlotView& sv, int t, float2* ld
   constexpr int NI = 2 * QH;  // spectrum registers that can hold a used subcarrier
   static_assert(NI <= Sh::P, "window wider than the lane's spectrum");
   const int A = sv.A, T = sv.T, CP = sv.CP, U = sv.U, B = sv.B;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int f = lane / Sh::L, li = lane % Sh::L;
+  // transform slot ts = tid / L; group tg = ts / F: the wavefront, or the
+  // wavefront pair of a two-wavefront transform
+  const int li = threadIdx.x % Sh::L, ts = threadIdx.x / Sh::L;
+  const int f = ts % Sh::F, tg = ts / Sh::F;
+  constexpr int NG = W / Sh::WPT;  // transform groups per workgroup
   const float2* Hs = sv.H;
   const uint32_t* iq = sv.iq;
 
@@ -230,25 +243,29 @@ __device__ __forceinline__ void demod_tile(const SlotView& sv, int t, float2* ld
   }
 
   // C symbols (antennas) per lane per iteration; antenna of lane group f and
-  // slot c in job J: J*F*C + c*F + f.  Job J = iteration * W + wave.
+  // slot c in job J: J*F*C + c*F + f.  Job J = iteration * NG + tg.
   constexpr int C = Sh::F == 1 ? RX_DEMOD_ILP : 1;
   float2* bufs[C];
 #pragma unroll
-  for (int c = 0; c < C; c++) bufs[c] = lds + ((wave * C + c) * Sh::F + f) * Lds<N>::kSlot;
+  for (int c = 0; c < C; c++) bufs[c] = lds + ((tg * C + c) * Sh::F + f) * Lds<N>::kSlot;
   float2* const(&buf)[C] = bufs;
   const int64_t sym_base = ((int64_t)t * A) * (N + CP) + CP;
-  // Software pipeline over this wavefront's antennas: each job's samples are
+  // Software pipeline over this group's antennas: each job's samples are
   // requested D jobs ahead.
   constexpr int JA = Sh::F * C;  // antennas per job
-  const int a_step = W * JA;
-  int a0 = wave * JA;
+  const int a_step = NG * JA;
+  int a0 = tg * JA;
   constexpr int D = RX_DEMOD_PREFETCH;
   static_assert(D == 1 || D == 2, "prefetch depth 1 or 2");
+  // A job's antennas past A read a valid record (the job's first antenna, or
+  // antenna A-1 for a two-wavefront transform, whose job may lie wholly past
+  // A) and add nothing (their channel rows are taken as zero).
+  auto valid_row = [&](int a, int aj) { return a < A ? a : (Sh::WPT > 1 ? A - 1 : aj); };
   auto request = [&](uint32_t (&dst)[C][Sh::P], int aj) {
 #pragma unroll
     for (int c = 0; c < C; c++) {
       const int a = aj + c * Sh::F + f;
-      load_symbol<N>(dst[c], iq + sym_base + (int64_t)(a < A ? a : aj) * (N + CP), li, a < A);
+      load_symbol<N>(dst[c], iq + sym_base + (int64_t)valid_row(a, aj) * (N + CP), li, a < A);
     }
   };
   // One job: its samples are in `cur`; once unpacked, `cur` is refilled with
@@ -265,12 +282,12 @@ __device__ __forceinline__ void demod_tile(const SlotView& sv, int t, float2* ld
     for (int c = 0; c < C; c++) {
       const int a = aj + c * Sh::F + f;
       const bool ok = a < A;
-      const float2* hrow = Hs + (int64_t)(ok ? a : aj) * U;
+      const float2* hrow = Hs + (int64_t)valid_row(a, aj) * U;
 #pragma unroll
       for (int i = 0; i < NI; i++) {
         const float2 hv = hrow[dcl(i)];
-        // a lane group whose antenna is past A must add nothing to its row
-        h[c][i] = (Sh::F == 1 || ok) ? hv : make_float2(0.f, 0.f);
+        // a transform whose antenna is past A must add nothing to its row
+        h[c][i] = ((Sh::F == 1 && Sh::WPT == 1) || ok) ? hv : make_float2(0.f, 0.f);
       }
     }
     if (aj + D * a_step < A) request(cur, aj + D * a_step);
@@ -292,30 +309,43 @@ __device__ __forceinline__ void demod_tile(const SlotView& sv, int t, float2* ld
           g[i] = fmaf(hh.x, hh.x, fmaf(hh.y, hh.y, g[i]));
         }
       }
-    wave_fence();  // this job's LDS reads precede the next job's writes
+    exchange_fence<N>();  // this job's LDS reads precede the next job's writes
   };
   // D sample buffers used round robin by a loop unrolled D times, so no
   // register copies (which would wait for the loads) are needed.
   uint32_t nxt[D][C][Sh::P];
+  if constexpr (Sh::WPT == 1) {
 #pragma unroll
-  for (int d = 0; d < D; d++)
-    if (a0 + d * a_step < A) request(nxt[d], a0 + d * a_step);
-  for (; a0 < A; a0 += D * a_step) {
-    job(nxt[0], a0);
-    if constexpr (D == 2) {
-      if (a0 + a_step < A) job(nxt[1], a0 + a_step);
+    for (int d = 0; d < D; d++)
+      if (a0 + d * a_step < A) request(nxt[d], a0 + d * a_step);
+    for (; a0 < A; a0 += D * a_step) {
+      job(nxt[0], a0);
+      if constexpr (D == 2) {
+        if (a0 + a_step < A) job(nxt[1], a0 + a_step);
+      }
+    }
+  } else {
+    // Exchange fences are workgroup barriers: every group runs the same
+    // number of jobs, counted from the workgroup's first antenna.
+#pragma unroll
+    for (int d = 0; d < D; d++) request(nxt[d], a0 + d * a_step);
+    for (int base = 0; base < A; base += D * a_step) {
+      job(nxt[0], base + a0);
+      if constexpr (D == 2) {
+        if (base + a_step < A) job(nxt[1], base + a_step + a0);
+      }
     }
   }
 
-  // Cross-wave reduction in a fixed order: row = wave * F + f holds the
-  // partial sums of one group of antennas for every used subcarrier (each
-  // subcarrier sits in exactly one lane of a transform's lane group; h = 0
-  // made invalid antennas contribute zeros).
-  constexpr int ROWS = W * Sh::F;
+  // Cross-group reduction in a fixed order: row ts holds the partial sums of
+  // one transform slot's antennas for every used subcarrier (each subcarrier
+  // sits in exactly one lane of a transform; h = 0 made invalid antennas
+  // contribute zeros).
+  constexpr int ROWS = NG * Sh::F;
   __syncthreads();
   float2* rz = lds;                                      // [ROWS][U]
   float* rg = reinterpret_cast<float*>(lds + ROWS * U);  // [ROWS][U]
-  const int row = wave * Sh::F + f;
+  const int row = ts;
 #pragma unroll
   for (int i = 0; i < NI; i++) {
     if (wok(i)) {
@@ -432,8 +462,8 @@ __global__ __launch_bounds__(64 * W) void batch_estimate_kernel(const FrameDesc*
     const int tile = next_tile(queue, n_tiles, tile_frame, &tile_sh, &frame_sh, frame);
     if (tile >= n_tiles) break;
     const FrameDesc d = fd[frame];
-    const int a_first = (tile - d.est_tile0) * (W * FftShape<N>::F * J) + (threadIdx.x >> 6) * FftShape<N>::F;
-    estimate_tile<N, W, J>(io.iq + d.iq_off, d.A, d.CP, d.U, d.pf, io.H + d.h_off, a_first, lds, twr, 1);
+    const int a_wg = (tile - d.est_tile0) * (transforms_per_group<N, W>() * J);
+    estimate_tile<N, W, J>(io.iq + d.iq_off, d.A, d.CP, d.U, d.pf, io.H + d.h_off, a_wg, lds, twr, 1);
   }
 }
 
@@ -497,18 +527,21 @@ __global__ __launch_bounds__(64 * W) void fft_kernel(const uint32_t* __restrict_
                                                      int blocks_per_sym) {
   using Sh = FftShape<N>;
   extern __shared__ float2 lds[];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int f = lane / Sh::L, li = lane % Sh::L;
+  const int li = threadIdx.x % Sh::L, ts = threadIdx.x / Sh::L;
+  const int f = ts % Sh::F;
   const int64_t st = blockIdx.x / blocks_per_sym;  // s * T + t
   const int blk = blockIdx.x % blocks_per_sym;
-  const int a0 = (blk * W + wave) * Sh::F;
+  const int a_wg = blk * transforms_per_group<N, W>();
+  // first antenna of this thread's wavefront; for a two-wavefront transform
+  // the workgroup's first (the exchange fences are workgroup barriers)
+  const int a0 = Sh::WPT > 1 ? a_wg : a_wg + ts - f;
   __shared__ float2 twtab[FftTwiddles<N>::kLdsFloat2 > 0 ? FftTwiddles<N>::kLdsFloat2 : 1];
   if constexpr (FftTwiddles<N>::kLdsLast) {
     FftTwiddles<N>::P3Lds::fill(twtab, tw, threadIdx.x, blockDim.x);
     __syncthreads();
   }
-  if (a0 >= A) return;  // no workgroup barrier below
-  const int a = a0 + f;
+  if (a0 >= A) return;  // uniform over whoever shares an exchange fence
+  const int a = a_wg + ts;
   const bool valid = a < A;
   const uint32_t* rec = iq + (st * A + (valid ? a : a0)) * (int64_t)(N + CP) + CP;
   uint32_t raw[Sh::P];
@@ -517,7 +550,7 @@ __global__ __launch_bounds__(64 * W) void fft_kernel(const uint32_t* __restrict_
   twr.load(tw, li, twtab);
   float2 v[Sh::P];
   unpack_symbol<N>(v, raw);
-  fft_in_regs<N>(v, lds + (wave * Sh::F + f) * Lds<N>::kSlot, li, twr);
+  fft_in_regs<N>(v, lds + ts * Lds<N>::kSlot, li, twr);
   if (valid) {
     float2* out = Y + (st * A + a) * (int64_t)N;
 #pragma unroll
@@ -532,9 +565,10 @@ constexpr int kJobsEst = RX_EST_JOBS;  // jobs per estimate wavefront
 constexpr int kWavesDemod = RX_DEMOD_WAVES;
 constexpr int kWavesFft = 4;
 
-template <int N>
-size_t fft_lds_bytes(int waves) {
-  return (size_t)waves * FftShape<N>::F * Lds<N>::kSlot * sizeof(float2);
+// Exchange buffers of a workgroup of W wavefronts: one per transform.
+template <int N, int W>
+size_t fft_lds_bytes() {
+  return (size_t)transforms_per_group<N, W>() * Lds<N>::kSlot * sizeof(float2);
 }
 
 // Dynamic LDS above 64 KB must be allowed per kernel before launching it.
@@ -547,11 +581,10 @@ hipError_t allow_lds(K kernel, size_t bytes) {
 
 template <int N>
 hipError_t estimate_n(const LaunchArgs& la, float2* H) {
-  using Sh = FftShape<N>;
-  const int per_block = kWavesEst * Sh::F * kJobsEst;  // antennas per workgroup
+  const int per_block = transforms_per_group<N, kWavesEst>() * kJobsEst;  // antennas per workgroup
   const int bps = (la.A + per_block - 1) / per_block;
   const int64_t grid = la.S * bps;
-  const size_t lds = fft_lds_bytes<N>(kWavesEst);
+  const size_t lds = fft_lds_bytes<N, kWavesEst>();
   hipError_t e = allow_lds(estimate_kernel<N, kWavesEst, kJobsEst>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((estimate_kernel<N, kWavesEst, kJobsEst>), dim3((unsigned)grid), dim3(64 * kWavesEst), lds,
@@ -561,11 +594,10 @@ hipError_t estimate_n(const LaunchArgs& la, float2* H) {
 
 template <int N>
 hipError_t fft_n(const LaunchArgs& la, float2* Y) {
-  using Sh = FftShape<N>;
-  const int jobs = (la.A + Sh::F - 1) / Sh::F;
-  const int bps = (jobs + kWavesFft - 1) / kWavesFft;
+  constexpr int TPW = transforms_per_group<N, kWavesFft>();
+  const int bps = (la.A + TPW - 1) / TPW;
   const int64_t grid = la.S * la.T * bps;
-  const size_t lds = fft_lds_bytes<N>(kWavesFft);
+  const size_t lds = fft_lds_bytes<N, kWavesFft>();
   hipError_t e = allow_lds(fft_kernel<N, kWavesFft>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((fft_kernel<N, kWavesFft>), dim3((unsigned)grid), dim3(64 * kWavesFft), lds, la.stream, la.iq, la.A, la.T, la.CP, la.tw, Y, bps);
@@ -576,8 +608,8 @@ template <int N, int QH, bool ZF>
 hipError_t demod_qh(const LaunchArgs& la, const float2* H, float2* xhat, uint8_t* bits) {
   const int64_t grid = la.S * (la.T - 1);
   constexpr int C = FftShape<N>::F == 1 ? RX_DEMOD_ILP : 1;
-  size_t lds = fft_lds_bytes<N>(kWavesDemod) * C;
-  const size_t red = (size_t)kWavesDemod * FftShape<N>::F * la.U * (sizeof(float2) + sizeof(float));
+  size_t lds = fft_lds_bytes<N, kWavesDemod>() * C;
+  const size_t red = (size_t)transforms_per_group<N, kWavesDemod>() * la.U * (sizeof(float2) + sizeof(float));
   if (red > lds) lds = red;
   hipError_t e = allow_lds(demod_kernel<N, QH, kWavesDemod, ZF>, lds);
   if (e != hipSuccess) return e;
@@ -589,19 +621,13 @@ hipError_t demod_qh(const LaunchArgs& la, const float2* H, float2* xhat, uint8_t
 // Register-window tiers: the smallest instantiated QH >= ceil((U/2 + 1) / L).
 template <int N, bool ZF>
 hipError_t demod_n(const LaunchArgs& la, const float2* H, float2* xhat, uint8_t* bits) {
-  constexpr int P = FftShape<N>::P, L = FftShape<N>::L;
+  constexpr int L = FftShape<N>::L;
+  static_assert(FftShape<N>::P == 16, "tiers assume 16 points per lane");
   const int need = (la.U / 2 + 1 + L - 1) / L;
-  if constexpr (P == 16) {
-    if (need <= 2) return demod_qh<N, 2, ZF>(la, H, xhat, bits);
-    if (need <= 4) return demod_qh<N, 4, ZF>(la, H, xhat, bits);
-    if (need <= 5) return demod_qh<N, 5, ZF>(la, H, xhat, bits);
-    if (need <= 8) return demod_qh<N, 8, ZF>(la, H, xhat, bits);
-  } else {
-    if (need <= 4) return demod_qh<N, 4, ZF>(la, H, xhat, bits);
-    if (need <= 8) return demod_qh<N, 8, ZF>(la, H, xhat, bits);
-    if (need <= 10) return demod_qh<N, 10, ZF>(la, H, xhat, bits);
-    if (need <= 16) return demod_qh<N, 16, ZF>(la, H, xhat, bits);
-  }
+  if (need <= 2) return demod_qh<N, 2, ZF>(la, H, xhat, bits);
+  if (need <= 4) return demod_qh<N, 4, ZF>(la, H, xhat, bits);
+  if (need <= 5) return demod_qh<N, 5, ZF>(la, H, xhat, bits);
+  if (need <= 8) return demod_qh<N, 8, ZF>(la, H, xhat, bits);
   return hipErrorInvalidValue;
 }
 
@@ -672,18 +698,17 @@ void est_entry(BatchKernel& k) {
 }
 template <int N, int W>
 bool demod_qh_pick(int need, BatchKernel& k) {
-  if constexpr (FftShape<N>::P == 16) {
-    if (need <= 5) { demod_entry<N, 5, W>(k); return true; }
-    if (need <= 8) { demod_entry<N, 8, W>(k); return true; }
-  } else {
-    if (need <= 10) { demod_entry<N, 10, W>(k); return true; }
-    if (need <= 16) { demod_entry<N, 16, W>(k); return true; }
-  }
+  static_assert(FftShape<N>::P == 16, "tiers assume 16 points per lane");
+  if (need <= 5) { demod_entry<N, 5, W>(k); return true; }
+  if (need <= 8) { demod_entry<N, 8, W>(k); return true; }
   return false;
 }
+// Transforms per workgroup of w wavefronts (w a multiple of the wavefronts per transform).
+template <int N>
+int tpw(int w) { return 64 * w / FftShape<N>::L; }
 template <int N>
 bool batch_pick_n(int max_u, int demod_waves, int est_jobs, BatchKernel& dem, BatchKernel& est) {
-  constexpr int L = FftShape<N>::L, F = FftShape<N>::F;
+  constexpr int L = FftShape<N>::L;
   const int need = (max_u / 2 + 1 + L - 1) / L;
   bool ok = false;
   switch (demod_waves) {
@@ -694,17 +719,17 @@ bool batch_pick_n(int max_u, int demod_waves, int est_jobs, BatchKernel& dem, Ba
   }
   if (!ok) return false;
   // LDS of the demod tile: exchange buffers, or the reduction rows if larger
-  dem.lds_fft = (size_t)demod_waves * F * Lds<N>::kSlot * sizeof(float2);
-  dem.lds_per_u = (size_t)demod_waves * F * (sizeof(float2) + sizeof(float));
+  dem.lds_fft = (size_t)tpw<N>(demod_waves) * Lds<N>::kSlot * sizeof(float2);
+  dem.lds_per_u = (size_t)tpw<N>(demod_waves) * (sizeof(float2) + sizeof(float));
   switch (est_jobs) {
     case 2: est_entry<N, 4, 2>(est); break;
     case 4: est_entry<N, 4, 4>(est); break;
     case 8: est_entry<N, 4, 8>(est); break;
     default: return false;
   }
-  est.lds_fft = (size_t)4 * F * Lds<N>::kSlot * sizeof(float2);
+  est.lds_fft = (size_t)tpw<N>(4) * Lds<N>::kSlot * sizeof(float2);
   est.lds_per_u = 0;
-  est.ants_per_tile = 4 * F * est_jobs;
+  est.ants_per_tile = tpw<N>(4) * est_jobs;
   dem.ants_per_tile = 0;
   return true;
 }

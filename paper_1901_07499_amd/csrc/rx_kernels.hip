@@ -222,6 +222,18 @@ __device__ __forceinline__ void demod_tile(const SlotView& sv, int t, float2* ld
     return i < QH ? (k >= 1 && k <= hU) : (k >= N - hU);
   };
   auto dcl = [&](int i) { return min(max(li + doff(i), 0), U - 1); };
+  // One transform per wavefront or pair (F == 1): channel rows are read
+  // through a buffer resource over the slot's estimate (A*U*8 < 2^31 bytes;
+  // reads past it would return zero) at byte offsets hoff[i] within a row.
+  const __amdgpu_buffer_rsrc_t hrs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<float2*>(Hs), (short)0, A * U * 8, 0x00020000);
+  const __amdgpu_buffer_rsrc_t hrs_empty =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<float2*>(Hs), (short)0, 0, 0x00020000);
+  int hoff[Sh::F == 1 ? NI : 1];
+  if constexpr (Sh::F == 1) {
+#pragma unroll
+    for (int i = 0; i < NI; i++) hoff[i] = dcl(i) * 8;
+  }
   float2 z[NI];
   float g[NI];
 #pragma unroll
@@ -282,12 +294,26 @@ __device__ __forceinline__ void demod_tile(const SlotView& sv, int t, float2* ld
     for (int c = 0; c < C; c++) {
       const int a = aj + c * Sh::F + f;
       const bool ok = a < A;
-      const float2* hrow = Hs + (int64_t)valid_row(a, aj) * U;
+      float2 hv[NI];
+      if constexpr (Sh::F == 1) {
+        // the antenna is uniform over the wavefront: row offset in a scalar
+        // register, per-lane offsets loop-invariant, no address arithmetic; a
+        // transform past A reads through an empty resource, which returns 0
+        const int au = __builtin_amdgcn_readfirstlane(a);
+        const int so = (au < A ? au : A - 1) * (U * 8);
+        const __amdgpu_buffer_rsrc_t rs = (Sh::WPT == 1 || au < A) ? hrs : hrs_empty;
+#pragma unroll
+        for (int i = 0; i < NI; i++)
+          hv[i] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, hoff[i], so, 0));
+      } else {
+        const float2* hrow = Hs + (int64_t)valid_row(a, aj) * U;
+#pragma unroll
+        for (int i = 0; i < NI; i++) hv[i] = hrow[dcl(i)];
+      }
 #pragma unroll
       for (int i = 0; i < NI; i++) {
-        const float2 hv = hrow[dcl(i)];
         // a transform whose antenna is past A must add nothing to its row
-        h[c][i] = ((Sh::F == 1 && Sh::WPT == 1) || ok) ? hv : make_float2(0.f, 0.f);
+        h[c][i] = (Sh::F == 1 || ok) ? hv[i] : make_float2(0.f, 0.f);
       }
     }
     if (aj + D * a_step < A) request(cur, aj + D * a_step);

@@ -120,7 +120,7 @@ def bench_batch(args):
     iq = torch.from_numpy(bt.iq).to(dev)
     out = batch.outputs(dev, want_H=False)
     t0 = time.time()
-    batch.autotune(iq, out, reps=2)
+    batch.autotune(iq, out, reps=8)
     classes = sorted({c.fft_len for c in bt.configs})
     chosen = {n: batch.config(n) for n in classes}
     log(f"autotuned in {time.time() - t0:.1f} s: {chosen}")

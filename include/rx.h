@@ -194,8 +194,10 @@ int rx_batch_process(rx_batch_t batch, const int16_t* iq, float* H, float* xhat,
                      void* workspace, void* hip_stream);
 
 /* Time every launch configuration of every FFT-length class on these buffers
- * (reps timed runs each, after one warm-up) and keep the fastest.
- * Synchronous; overwrites the outputs. */
+ * (reps timed runs each after one warm-up, the minimum counts): first each
+ * class alone, then, class by class from the longest, within the whole batch
+ * graph with the other classes as chosen so far; keeps the configuration with
+ * the shortest batch.  Synchronous; overwrites the outputs. */
 int rx_batch_autotune(rx_batch_t batch, const int16_t* iq, float* H, float* xhat, uint8_t* bits,
                       void* workspace, int32_t reps, void* hip_stream);
 

@@ -85,6 +85,50 @@ constexpr int transforms_per_group() {
   return 64 * W / FftShape<N>::L;
 }
 
+// Per-lane constants of the estimate: the subcarrier of each spectrum
+// register (-1 when its bin is unused) and that subcarrier's pilot factor.
+template <int N>
+struct EstLane {
+  int dq[FftShape<N>::P];
+  float2 pq[FftShape<N>::P];
+  __device__ __forceinline__ void init(int li, int U, const float2* __restrict__ pf) {
+#pragma unroll
+    for (int q = 0; q < FftShape<N>::P; q++) {
+      dq[q] = sub_of_bin(li + FftShape<N>::L * q, N, U);
+      pq[q] = pf[dq[q] >= 0 ? dq[q] : 0];  // clamped load; unused bins are never stored
+    }
+  }
+};
+
+// One pilot symbol (samples unpacked into v): FFT, LS by the pilot factors,
+// H row out (hrow null: nothing stored).  With a comb pilot (every ps-th used
+// subcarrier) the LS values go to the transform's LDS slot and every
+// subcarrier is interpolated from them.  Ends with an exchange fence.
+template <int N>
+__device__ __forceinline__ void estimate_job(float2 (&v)[FftShape<N>::P], const EstLane<N>& el, float2* buf, int li,
+                                             const FftTwiddles<N>& twr, float2* __restrict__ hrow, int U, int ps) {
+  using Sh = FftShape<N>;
+  fft_in_regs<N>(v, buf, li, twr);
+  if (ps <= 1) {
+    if (hrow) {
+#pragma unroll
+      for (int q = 0; q < Sh::P; q++)
+        if (el.dq[q] >= 0) hrow[el.dq[q]] = cmul(v[Spectrum<N>::reg(q)], el.pq[q]);
+    }
+  } else {
+    // comb: LS on the pilot subcarriers into this transform's LDS slot (the
+    // FFT's last LDS reads are behind), then every subcarrier
+    exchange_fence<N>();
+#pragma unroll
+    for (int q = 0; q < Sh::P; q++)
+      if (el.dq[q] >= 0 && el.dq[q] % ps == 0) buf[el.dq[q] / ps] = cmul(v[Spectrum<N>::reg(q)], el.pq[q]);
+    exchange_fence<N>();
+    if (hrow)
+      for (int d = li; d < U; d += Sh::L) hrow[d] = comb_value(buf, d, U, ps);
+  }
+  exchange_fence<N>();  // this job's LDS reads precede the next job's writes
+}
+
 // LS estimate of one slot's antennas a_wg .. a_wg + TPW*J - 1: transform slot
 // ts = tid / L of the workgroup takes antennas a_wg + ts + j*TPW, j < J, the
 // next job's samples requested before the current transform.  slot_iq: the
@@ -104,15 +148,8 @@ __device__ __forceinline__ void estimate_tile(const uint32_t* __restrict__ slot_
   // workgroup's first when a transform spans wavefronts
   const int a_lead = Sh::WPT > 1 ? a_wg : a_wg + ts - f;
   if (a_lead >= A) return;
-  // subcarrier of each spectrum register (clamped for the pilot-factor load;
-  // unused bins are never stored) and its pilot factor
-  int dq[Sh::P];
-  float2 pq[Sh::P];
-#pragma unroll
-  for (int q = 0; q < Sh::P; q++) {
-    dq[q] = sub_of_bin(li + Sh::L * q, N, U);
-    pq[q] = pf[dq[q] >= 0 ? dq[q] : 0];
-  }
+  EstLane<N> el;
+  el.init(li, U, pf);
   const uint32_t* pilot_sym = slot_iq + CP;  // symbol 0
   // record of antenna a, or of the (valid) lead antenna lead when a >= A
   auto rec_of = [&](int a, int lead) { return pilot_sym + (int64_t)(a < A ? a : lead) * (N + CP); };
@@ -127,28 +164,7 @@ __device__ __forceinline__ void estimate_tile(const uint32_t* __restrict__ slot_
     float2 v[Sh::P];
     unpack_symbol<N>(v, nxt);
     if (j + 1 < J && lead + TPW < A) load_symbol<N>(nxt, rec_of(a + TPW, lead + TPW), li, a + TPW < A);
-    fft_in_regs<N>(v, buf, li, twr);
-    if (ps <= 1) {
-      if (a < A) {
-        float2* hrow = Hs + (int64_t)a * U;
-#pragma unroll
-        for (int q = 0; q < Sh::P; q++)
-          if (dq[q] >= 0) hrow[dq[q]] = cmul(v[Spectrum<N>::reg(q)], pq[q]);
-      }
-    } else {
-      // comb: LS on the pilot subcarriers into this transform's LDS slot
-      // (the FFT's last LDS reads are behind), then every subcarrier
-      exchange_fence<N>();
-#pragma unroll
-      for (int q = 0; q < Sh::P; q++)
-        if (dq[q] >= 0 && dq[q] % ps == 0) buf[dq[q] / ps] = cmul(v[Spectrum<N>::reg(q)], pq[q]);
-      exchange_fence<N>();
-      if (a < A) {
-        float2* hrow = Hs + (int64_t)a * U;
-        for (int d = li; d < U; d += Sh::L) hrow[d] = comb_value(buf, d, U, ps);
-      }
-    }
-    exchange_fence<N>();  // this job's LDS reads precede the next job's writes
+    estimate_job<N>(v, el, buf, li, twr, a < A ? Hs + (int64_t)a * U : nullptr, U, ps);
   }
 }
 
@@ -180,6 +196,56 @@ __global__ __launch_bounds__(64 * W) void estimate_kernel(const uint32_t* __rest
                          ps);
 }
 
+// Uniform slots, one transform per wavefront (N = 1024): a grid of resident
+// workgroups only; transform g of the grid (G in all) takes jobs g, g + G, ...
+// of the S*A list of (slot, antenna) pilot symbols, the next job's samples
+// requested before the current transform.  Every wavefront then ends within
+// one job of the others, where (slot, group) workgroups leave a partial last
+// round of workgroups running alone whenever their count exceeds what the
+// GPU holds at once (c2: 3200 wavefronts against 3072 resident).
+template <int N, int W>
+__global__ __launch_bounds__(64 * W) void estimate_grid_kernel(const uint32_t* __restrict__ iq, int64_t S, int A,
+                                                               int T, int CP, int U, const float2* __restrict__ tw,
+                                                               const float2* __restrict__ pf,
+                                                               float2* __restrict__ H, int ps) {
+  using Sh = FftShape<N>;
+  static_assert(Sh::F == 1 && Sh::WPT == 1, "one transform per wavefront");
+  extern __shared__ float2 lds[];
+  __shared__ float2 twtab[FftTwiddles<N>::kLdsFloat2 > 0 ? FftTwiddles<N>::kLdsFloat2 : 1];
+  FftTwiddles<N> twr;
+  tile_setup<N>(twr, twtab, tw);
+  const int li = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t jobs = S * A;
+  const int64_t G = (int64_t)gridDim.x * W;
+  int64_t j = (int64_t)blockIdx.x * W + wave;  // uniform over the wavefront
+  if (j >= jobs) return;                       // no workgroup barrier below
+  EstLane<N> el;
+  el.init(li, U, pf);
+  // (slot, antenna) of job j, advanced by G per step without a division
+  const int Gs = (int)(G / A), Ga = (int)(G % A);
+  int64_t s = j / A;
+  int a = (int)(j - s * A);
+  auto rec = [&](int64_t ss, int aa) { return iq + (ss * T * A + aa) * (int64_t)(N + CP) + CP; };
+  float2* buf = lds + wave * Lds<N>::kSlot;
+  uint32_t nxt[Sh::P];
+  load_symbol<N>(nxt, rec(s, a), li, true);
+  for (; j < jobs; j += G) {
+    float2 v[Sh::P];
+    unpack_symbol<N>(v, nxt);
+    const int64_t s0 = s;
+    const int a0 = a;
+    s += Gs;
+    a += Ga;
+    if (a >= A) {
+      a -= A;
+      s++;
+    }
+    if (j + G < jobs) load_symbol<N>(nxt, rec(s, a), li, true);
+    estimate_job<N>(v, el, buf, li, twr, H + (s0 * A + a0) * (int64_t)U, U, ps);
+  }
+}
+
 // ------------------------------------------------------------------ demod
 // One slot as seen by the per-tile routines (pointers already offset to the
 // slot; outputs may be null).
@@ -199,7 +265,7 @@ __device__ __forceinline__ void demod_tile(const SlotView& sv, int t, float2* ld
   using Sh = FftShape<N>;
   constexpr int NI = 2 * QH;  // spectrum registers that can hold a used subcarrier
   static_assert(NI <= Sh::P, "window wider than the lane's spectrum");
-  const int A = sv.A, T = sv.T, CP = sv.CP, U = sv.U, B = sv.B;
+  const int A = sv.A, CP = sv.CP, U = sv.U, B = sv.B;
   // transform slot ts = tid / L; group tg = ts / F: the wavefront, or the
   // wavefront pair of a two-wavefront transform
   const int li = threadIdx.x % Sh::L, ts = threadIdx.x / Sh::L;
@@ -605,8 +671,36 @@ hipError_t allow_lds(K kernel, size_t bytes) {
                              (int)bytes);
 }
 
+// Workgroups of `kernel` (block threads, lds bytes) the device holds at once,
+// cached per device.
+template <typename K>
+int resident_groups(K kernel, int block, size_t lds) {
+  static int cached[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 0;
+  if (dev < 64 && cached[dev] > 0) return cached[dev];
+  int cus = 0, per_cu = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kernel), block, lds) !=
+          hipSuccess)
+    return 0;
+  const int n = cus * (per_cu > 0 ? per_cu : 1);
+  if (dev < 64) cached[dev] = n;
+  return n;
+}
+
 template <int N>
 hipError_t estimate_n(const LaunchArgs& la, float2* H) {
+  if constexpr (FftShape<N>::F == 1 && FftShape<N>::WPT == 1) {
+    const size_t lds = fft_lds_bytes<N, kWavesEst>();
+    const int resident = resident_groups(estimate_grid_kernel<N, kWavesEst>, 64 * kWavesEst, lds);
+    if (resident <= 0) return hipErrorInvalidValue;
+    const int64_t needed = (la.S * la.A + kWavesEst - 1) / kWavesEst;
+    const int64_t grid = needed < resident ? needed : resident;
+    hipLaunchKernelGGL((estimate_grid_kernel<N, kWavesEst>), dim3((unsigned)grid), dim3(64 * kWavesEst), lds,
+                       la.stream, la.iq, la.S, la.A, la.T, la.CP, la.U, la.tw, la.pf, H, la.ps);
+    return hipGetLastError();
+  }
   const int per_block = transforms_per_group<N, kWavesEst>() * kJobsEst;  // antennas per workgroup
   const int bps = (la.A + per_block - 1) / per_block;
   const int64_t grid = la.S * bps;

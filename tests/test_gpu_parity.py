@@ -81,6 +81,9 @@ CASES = {
     "N512_A7_16qam": C2.replace(n_ant=7, fft_len=512, cp_len=37, n_used=300, bits_per_sym=4, n_slots=2),
     "N2048_A9_64qam": C4.replace(n_ant=9, n_slots=2, n_sym=4),
     "N2048_A1": C4.replace(n_ant=1, n_slots=2, n_sym=3),
+    # more pilot symbols (3700) than a MI355X holds estimate transforms at once (3072): the
+    # resident-grid estimate walks its job list more than once, stepping (slot, antenna)
+    "A37_S100_estimate_grid_wraps": C2.replace(n_ant=37, n_sym=2, n_slots=100),
     "N2048_A2_qpsk": C4.replace(n_ant=2, bits_per_sym=2, n_slots=3, n_sym=3),
     "A1": C2.replace(n_ant=1, n_slots=2, n_sym=4),
     "U2_minimal": C2.replace(n_ant=4, n_used=2, n_slots=1, n_sym=3),

@@ -671,21 +671,29 @@ hipError_t allow_lds(K kernel, size_t bytes) {
                              (int)bytes);
 }
 
-// Workgroups of `kernel` (block threads, lds bytes) the device holds at once,
-// cached per device.
+// Workgroups of `kernel` (block threads, lds bytes) the current device holds at
+// once.  Callers cache the answer per device and kernel instantiation.
 template <typename K>
-int resident_groups(K kernel, int block, size_t lds) {
-  static int cached[64];
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 0;
-  if (dev < 64 && cached[dev] > 0) return cached[dev];
+int resident_groups(K kernel, int block, size_t lds, int dev) {
   int cus = 0, per_cu = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
       hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kernel), block, lds) !=
           hipSuccess)
     return 0;
-  const int n = cus * (per_cu > 0 ? per_cu : 1);
-  if (dev < 64) cached[dev] = n;
+  return cus * (per_cu > 0 ? per_cu : 1);
+}
+
+// Resident workgroups of estimate_grid_kernel<N, W> on the current device
+// (0 on error), cached per device for this instantiation; concurrent first
+// calls store the same value.
+template <int N, int W>
+int estimate_grid_capacity(size_t lds) {
+  static int cached[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 0;
+  if (dev < 64 && cached[dev] > 0) return cached[dev];
+  const int n = resident_groups(estimate_grid_kernel<N, W>, 64 * W, lds, dev);
+  if (dev < 64 && n > 0) cached[dev] = n;
   return n;
 }
 
@@ -693,7 +701,7 @@ template <int N>
 hipError_t estimate_n(const LaunchArgs& la, float2* H) {
   if constexpr (FftShape<N>::F == 1 && FftShape<N>::WPT == 1) {
     const size_t lds = fft_lds_bytes<N, kWavesEst>();
-    const int resident = resident_groups(estimate_grid_kernel<N, kWavesEst>, 64 * kWavesEst, lds);
+    const int resident = estimate_grid_capacity<N, kWavesEst>(lds);
     if (resident <= 0) return hipErrorInvalidValue;
     const int64_t needed = (la.S * la.A + kWavesEst - 1) / kWavesEst;
     const int64_t grid = needed < resident ? needed : resident;

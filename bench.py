@@ -437,7 +437,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4", "batch", "denoiser", "sync", "precision"])
     ap.add_argument("--frames", type=int, default=256, help="frames of the batch workload")
-    ap.add_argument("--slots", type=int, default=32, help="slots of the denoiser, sync and precision workloads")
+    ap.add_argument("--slots", type=int, default=None,
+                    help="slots of the denoiser (default 32), sync (32) and precision (500, its configuration) workloads")
     ap.add_argument("--quality-slots", type=int, default=8,
                     help="slots per SNR of the denoiser and precision quality figures")
     ap.add_argument("--dn-steps", type=int, default=2000, help="training steps of the denoiser workload")
@@ -467,6 +468,8 @@ def main():
               "so multi-GPU throughput is N x the one-GPU figure; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    if args.slots is None:
+        args.slots = 500 if args.workload == "precision" else 32
     if args.workload == "batch":
         bench_batch(args)
         return

@@ -441,8 +441,9 @@ def main():
                     help="slots of the denoiser (default 32), sync (32) and precision (500, its configuration) workloads")
     ap.add_argument("--quality-slots", type=int, default=8,
                     help="slots per SNR of the denoiser and precision quality figures")
-    ap.add_argument("--dn-steps", type=int, default=2000, help="training steps of the denoiser workload")
-    ap.add_argument("--dn-rows", type=int, default=256, help="rows (antenna estimates) per training step")
+    # 25 000 steps x 1024 rows = 25.6 M antenna rows = 200 k slots of 128 antennas, the configured budget
+    ap.add_argument("--dn-steps", type=int, default=25000, help="training steps of the denoiser workload")
+    ap.add_argument("--dn-rows", type=int, default=1024, help="rows (antenna estimates) per training step")
     ap.add_argument("--dn-lr", type=float, default=2e-3, help="Adam learning rate")
     ap.add_argument("--workers", type=int, default=0,
                     help="generator processes for the denoiser and precision workloads (0 = up to 16; "

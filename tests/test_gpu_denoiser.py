@@ -68,6 +68,20 @@ def test_comb_estimate_matches_oracle(rx, N, cp, U, s, A):
     check_H(H, ref.H)
 
 
+def test_comb_estimate_when_the_estimate_grid_wraps(rx):
+    # 37 antennas x 100 slots = 3700 pilot symbols, more than a MI355X holds estimate transforms
+    # at once (3072): the N = 1024 estimate walks its job list more than once
+    cfg = C5.replace(n_ant=37, fft_len=1024, cp_len=72, n_used=600, pilot_spacing=3, n_sym=2, bits_per_sym=4,
+                     tau_max_us=(0.5, 2.0))
+    _say("comb estimate, grid wraps", cfg.seed)
+    fr = make_frames(cfg, n_slots=100)
+    plan = rx.Plan.from_config(cfg, fr.pilot)
+    H = as_complex(plan.estimate(torch.from_numpy(fr.iq).cuda()))
+    torch.cuda.synchronize()
+    ref = oracle.process_frame(fr.iq, fr.pilot, **_kw(cfg))
+    check_H(H, ref.H)
+
+
 def test_comb_path_end_to_end_c5_shape(rx):
     cfg = C5.replace(n_slots=2)
     _say("comb path c5 shape", cfg.seed)

@@ -175,6 +175,30 @@ __device__ __forceinline__ void store_masks(const bfbits* __restrict__ X, int t0
   }
 }
 
+// ReLU of a unit's outputs (lane r holds position p0 + r), zero for positions
+// outside the row [0, U).  The ReLU is a signed-integer max of the float's
+// bits: positive floats order as positive integers, negative ones and -0 as
+// negative, so max(bits, 0) is max(x, +0) for every non-NaN x -- one
+// instruction per value, where a float max first canonicalises its operand.
+// Only units that reach past an end of the row (a wavefront-uniform test)
+// pay for the position mask.
+__device__ __forceinline__ float relu_bits(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+__device__ __forceinline__ void relu_unit(f32x4 (&acc)[2], int p0, int U) {
+  if (p0 >= 0 && p0 + 15 < U) {
+#pragma unroll
+    for (int h = 0; h < 2; h++)
+#pragma unroll
+      for (int i = 0; i < 4; i++) acc[h][i] = relu_bits(acc[h][i]);
+  } else {
+    const int p = p0 + (threadIdx.x & 15);
+    const bool in = p >= 0 && p < U;
+#pragma unroll
+    for (int h = 0; h < 2; h++)
+#pragma unroll
+      for (int i = 0; i < 4; i++) acc[h][i] = in ? relu_bits(acc[h][i]) : 0.f;
+  }
+}
+
 __device__ __forceinline__ void bias_init(f32x4 (&acc)[2], const float* __restrict__ b) {
   const int q = (threadIdx.x & 63) >> 4;
 #pragma unroll
@@ -265,10 +289,7 @@ __global__ __launch_bounds__(kBlock) void dn_forward_kernel(const float2* __rest
         acc[0] = mfma(w1[0], bv, acc[0]);
         acc[1] = mfma(w1[1], bv, acc[1]);
         const bool in = p >= 0 && p < U;
-#pragma unroll
-        for (int h = 0; h < 2; h++)
-#pragma unroll
-          for (int i = 0; i < 4; i++) acc[h][i] = in ? fmaxf(acc[h][i], 0.f) : 0.f;
+        relu_unit(acc, t0 - 9 + 16 * u, U);
         store_unit(XA, idx, acc);
         if (TRAIN && in && p >= t0 && p < t0 + TO) store_global(io.X1 + row * 32 * UP, UP, p, acc);
       }
@@ -282,10 +303,7 @@ __global__ __launch_bounds__(kBlock) void dn_forward_kernel(const float2* __rest
         bias_init(acc, b2);
         unit32<1>(XA, 6 + 16 * u - 3, w2, acc);
         const bool in = p >= 0 && p < U;
-#pragma unroll
-        for (int h = 0; h < 2; h++)
-#pragma unroll
-          for (int i = 0; i < 4; i++) acc[h][i] = in ? fmaxf(acc[h][i], 0.f) : 0.f;
+        relu_unit(acc, t0 - 6 + 16 * u, U);
         store_unit(XB, idx, acc);
         if (TRAIN && in && p >= t0 && p < t0 + TO) store_global(io.X2 + row * 32 * UP, UP, p, acc);
       }
@@ -299,10 +317,7 @@ __global__ __launch_bounds__(kBlock) void dn_forward_kernel(const float2* __rest
         bias_init(acc, b3);
         unit32<1>(XB, 9 + 16 * u - 3, w3, acc);
         const bool in = p >= 0 && p < U;
-#pragma unroll
-        for (int h = 0; h < 2; h++)
-#pragma unroll
-          for (int i = 0; i < 4; i++) acc[h][i] = in ? fmaxf(acc[h][i], 0.f) : 0.f;
+        relu_unit(acc, t0 - 3 + 16 * u, U);
         store_unit(XA, idx, acc);
         if (TRAIN && in && p >= t0 && p < t0 + TO) store_global(io.X3 + row * 32 * UP, UP, p, acc);
       }

@@ -124,6 +124,21 @@ __device__ __forceinline__ void unit32(const bfbits* __restrict__ X, int row0, c
   }
 }
 
+// The two halves of unit32, for software pipelining: the 7 tap operands of a
+// unit, then its 14 products.
+__device__ __forceinline__ void unit32_load(const bfbits* __restrict__ X, int row0, bf16x8 (&b)[7]) {
+  const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
+#pragma unroll
+  for (int k = 0; k < 7; k++) b[k] = as_bf16x8(*reinterpret_cast<const uint4*>(X + (row0 + k + r) * RS + 8 * q));
+}
+__device__ __forceinline__ void unit32_mma(const bf16x8 (&b)[7], const bf16x8 (&w)[2][7], f32x4 (&acc)[2]) {
+#pragma unroll
+  for (int k = 0; k < 7; k++) {
+    acc[0] = mfma(w[0][k], b[k], acc[0]);
+    acc[1] = mfma(w[1][k], b[k], acc[1]);
+  }
+}
+
 // Four dwords at dword index i of an LDS buffer of 2-channel positions
 // (4-byte aligned reads).
 __device__ __forceinline__ bf16x8 read4(const uint32_t* __restrict__ X, int i) {
@@ -205,6 +220,31 @@ __device__ __forceinline__ void bias_init(f32x4 (&acc)[2], const float* __restri
   for (int h = 0; h < 2; h++)
 #pragma unroll
     for (int i = 0; i < 4; i++) acc[h][i] = b[16 * h + 4 * q + i];
+}
+
+// A 32-input-channel layer of an inference tile: this wavefront's units
+// u = wave, wave + 4, ... (NU in all, a multiple of 4), with the next unit's
+// tap operands requested before the current unit's products so the LDS
+// latency overlaps the MFMAs.  Unit u covers LDS rows first + 16 u + r of the
+// output, reading rows from first + 16 u - 3; positions p0 + 16 u + r.
+template <int NU>
+__device__ __forceinline__ void layer32_pipelined(const bfbits* __restrict__ X, bfbits* __restrict__ Y, int first,
+                                                  int p0, int U, const bf16x8 (&w)[2][7],
+                                                  const float* __restrict__ bias) {
+  static_assert(NU % 4 == 0, "whole rounds of the 4 wavefronts");
+  const int wave = threadIdx.x >> 6, r = threadIdx.x & 15;
+  bf16x8 b[2][7];
+  unit32_load(X, first + 16 * wave - 3, b[0]);
+#pragma unroll
+  for (int j = 0; j < NU / 4; j++) {
+    const int u = wave + 4 * j;
+    if (j + 1 < NU / 4) unit32_load(X, first + 16 * (u + 4) - 3, b[(j + 1) & 1]);
+    f32x4 acc[2];
+    bias_init(acc, bias);
+    unit32_mma(b[j & 1], w, acc);
+    relu_unit(acc, p0 + 16 * u, U);
+    store_unit(Y, first + 16 * u + r, acc);
+  }
 }
 
 // ------------------------------------------------------------------ forward
@@ -296,7 +336,8 @@ __global__ __launch_bounds__(kBlock) void dn_forward_kernel(const float2* __rest
       __syncthreads();
       if (TRAIN) store_masks(XA, t0, U, io.M1 + row * UP);
       // layer 2: A -> B
-      for (int u = wave; u < U2; u += 4) {
+      if constexpr (!TRAIN) layer32_pipelined<U2>(XA, XB, 6, t0 - 6, U, w2, b2);
+      else for (int u = wave; u < U2; u += 4) {
         const int idx = 6 + 16 * u + r;
         const int p = t0 - 6 + 16 * u + r;
         f32x4 acc[2];
@@ -310,7 +351,8 @@ __global__ __launch_bounds__(kBlock) void dn_forward_kernel(const float2* __rest
       __syncthreads();
       if (TRAIN) store_masks(XB, t0, U, io.M2 + row * UP);
       // layer 3: B -> A
-      for (int u = wave; u < U3; u += 4) {
+      if constexpr (!TRAIN) layer32_pipelined<U3>(XB, XA, 9, t0 - 3, U, w3, b3);
+      else for (int u = wave; u < U3; u += 4) {
         const int idx = 9 + 16 * u + r;
         const int p = t0 - 3 + 16 * u + r;
         f32x4 acc[2];

@@ -156,7 +156,7 @@ def tap_delays_powers(cfg: FrameConfig, tau_max_s: float, n_taps: Optional[int] 
 
 @dataclasses.dataclass
 class Frames:
-    """One run of synthetic slots plus everything needed to judge a receiver."""
+    """One run of synthetic slots plus everything needed to evaluate a receiver."""
     cfg: FrameConfig
     iq: np.ndarray          # int16 [S][T][A][CP+N][2]
     pilot: np.ndarray       # complex128 [U], the known pilot symbol X_p[d]

@@ -313,7 +313,7 @@ int rx_dn_generate(const rx_chan_gen* gen, uint64_t seed, int64_t first_row, int
 
 /* Device scratch of rx_sync_find for n_ant antennas and n_search candidates
  * (per-antenna-group partial metrics and per-block maxima; at most
- * 64 * 8 * n_search bytes plus 16 per 256 candidates).  0 on bad arguments. */
+ * 64 * 8 * n_search bytes plus 16 per 64 candidates).  0 on bad arguments. */
 size_t rx_sync_workspace_bytes(int32_t n_ant, int64_t n_search);
 
 /* Correlation metric and peak.  raw: device, 4-byte aligned; 1 <= n_ant <= 4096;

@@ -12,9 +12,13 @@
 // sync_metric_kernel: workgroup = (1024 candidates, group of antennas); per
 // antenna the workgroup stages the samples its candidates need in LDS and
 // each thread correlates 4 consecutive candidates through a sliding register
-// window.  The per-group partial metrics are summed by sync_reduce_kernel
-// (integer sums: exact in any order), which also reduces each 256 candidates
-// to the best (M, n); sync_argmax_kernel reduces those in one workgroup.
+// window.  The staged samples sit in four planes by sample index mod 4, so
+// the window's reads (thread t, sample 4t + m) are consecutive across lanes
+// with compile-time offsets instead of a 4-dword stride (4-way LDS bank
+// conflicts).  The per-group partial metrics are summed by sync_reduce_kernel
+// (integer sums: exact in any order, 4 threads per candidate), which also
+// reduces each 64 candidates to the best (M, n); sync_argmax_kernel reduces
+// those in one workgroup.
 // "Best" = larger M, then smaller n: a total order, so the result does not
 // depend on the reduction order.
 // sync_extract_kernel: copies the slots that follow the preamble into the
@@ -32,6 +36,15 @@ namespace sync {
 constexpr int kThreads = 256;       // threads per metric workgroup
 constexpr int kTile = 4 * kThreads;  // candidates per metric workgroup
 constexpr int kMaxGroups = 64;       // antenna groups (grid.y) at most
+constexpr int kTargetGroups = 2048;  // metric workgroups aimed for (8 per CU)
+constexpr int kRedCand = 64;         // candidates per reduce workgroup (4 threads each)
+
+// Dwords per sample plane of the metric kernel's staging buffer: at least a
+// quarter of the staged samples, and 16 more than a multiple of 64 so the
+// four planes' rows fall in different LDS banks.
+__host__ __device__ constexpr int plane_dwords(int L) {
+  return ((kTile + L + 3 + 3) / 4 + 47) / 64 * 64 + 16;
+}
 
 struct Best {
   uint64_t v;
@@ -74,24 +87,26 @@ __device__ __forceinline__ void unpack(uint32_t s, int (&re)[Q], int (&im)[Q], i
 __global__ __launch_bounds__(kThreads) void sync_metric_kernel(const uint32_t* __restrict__ raw, int A, int ag,
                                                                int64_t n_samples, int64_t stride, SyncChips ch,
                                                                int64_t n_search, uint64_t* __restrict__ part) {
-  extern __shared__ uint32_t ys[];  // [kTile + L + 3]
+  extern __shared__ uint32_t ys[];  // 4 planes of plane_dwords(L): sample j at (j % 4) * P + j / 4
   const int tid = threadIdx.x, L = ch.L;
+  const int P = plane_dwords(L);
   const int64_t n0 = (int64_t)blockIdx.x * kTile;
   const int g = blockIdx.y, a0 = g * ag, a1 = min(A, a0 + ag);
   const int span = kTile + L + 3;
   uint64_t acc[4] = {0, 0, 0, 0};
+  // sample 4t + k of this thread's window: plane k % 4, row t + k / 4
+  auto Y = [&](int k) { return ys[(k & 3) * P + tid + (k >> 2)]; };
   for (int a = a0; a < a1; a++) {
     __syncthreads();  // the previous antenna's readers are done
     const uint32_t* ya = raw + (int64_t)a * stride;
     for (int j = tid; j < span; j += kThreads) {
       const int64_t i = n0 + j;
-      ys[j] = i < n_samples ? ya[i] : 0u;
+      ys[(j & 3) * P + (j >> 2)] = i < n_samples ? ya[i] : 0u;
     }
     __syncthreads();
-    const uint32_t* y = ys + 4 * tid;
     int wr[4], wi[4];
 #pragma unroll
-    for (int j = 0; j < 4; j++) unpack<4>(y[j], wr, wi, j);
+    for (int j = 0; j < 4; j++) unpack<4>(Y(j), wr, wi, j);
     int re[4] = {0, 0, 0, 0}, im[4] = {0, 0, 0, 0};
     // window slot (m + j) % 4 holds sample 4t + m + j
     int m = 0;
@@ -104,7 +119,7 @@ __global__ __launch_bounds__(kThreads) void sync_metric_kernel(const uint32_t* _
           re[j] += c * wr[(u + j) & 3];
           im[j] += c * wi[(u + j) & 3];
         }
-        unpack<4>(y[m + u + 4], wr, wi, u);  // slot u now holds sample 4t + m + u + 4
+        unpack<4>(Y(m + u + 4), wr, wi, u);  // slot u now holds sample 4t + m + u + 4
       }
     }
     for (; m < L; m++) {  // tail: rotate by hand
@@ -123,7 +138,7 @@ __global__ __launch_bounds__(kThreads) void sync_metric_kernel(const uint32_t* _
         im[j] += c * vi;
       }
       const int s = m & 3;
-      const uint32_t nx = y[m + 4];
+      const uint32_t nx = Y(m + 4);
 #pragma unroll
       for (int k = 0; k < 4; k++)
         if (s == k) unpack<4>(nx, wr, wi, k);
@@ -139,23 +154,31 @@ __global__ __launch_bounds__(kThreads) void sync_metric_kernel(const uint32_t* _
   }
 }
 
-// M[n] = sum over antenna groups (integers: any order is exact), plus the
-// best (M, n) of each workgroup.
+// M[n] = sum over antenna groups (integers: any order is exact), 4 threads
+// per candidate (wave w sums groups w, w + 4, ...), plus the best (M, n) of
+// each workgroup's kRedCand candidates.
 __global__ __launch_bounds__(256) void sync_reduce_kernel(const uint64_t* __restrict__ part, int G, int64_t n_search,
                                                           uint64_t* __restrict__ M, uint64_t* __restrict__ cand_v,
                                                           int64_t* __restrict__ cand_i) {
-  __shared__ Best sh[4];
-  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  __shared__ uint64_t sums[4][kRedCand];
+  const int c = threadIdx.x & (kRedCand - 1), w = threadIdx.x / kRedCand;
+  const int64_t n = (int64_t)blockIdx.x * kRedCand + c;
   const bool ok = n < n_search;
   uint64_t v = 0;
   if (ok)
-    for (int g = 0; g < G; g++) v += part[(int64_t)g * n_search + n];
-  if (ok && M) M[n] = v;
-  Best b = {ok ? v : 0ull, ok ? n : INT64_MAX};
-  b = block_best(b, sh);
-  if (threadIdx.x == 0) {
-    cand_v[blockIdx.x] = b.v;
-    cand_i[blockIdx.x] = b.i;
+    for (int g = w; g < G; g += 4) v += part[(int64_t)g * n_search + n];
+  sums[w][c] = v;
+  __syncthreads();
+  if (w == 0) {
+    v += sums[1][c] + sums[2][c] + sums[3][c];
+    if (ok && M) M[n] = v;
+    Best b = {ok ? v : 0ull, ok ? n : INT64_MAX};
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) b = better(b, shfl_xor(b, o));
+    if (c == 0) {
+      cand_v[blockIdx.x] = b.v;
+      cand_i[blockIdx.x] = b.i;
+    }
   }
 }
 
@@ -196,11 +219,11 @@ __global__ __launch_bounds__(256) void sync_extract_kernel(const uint32_t* __res
 
 }  // namespace sync
 
-// Antenna groups: enough workgroups to fill the GPU (about 512), at most one
-// group per antenna.
+// Antenna groups: enough workgroups to fill the GPU (about kTargetGroups), at
+// most one group per antenna.
 int sync_groups(int A, int64_t n_search) {
   const int64_t tiles = (n_search + sync::kTile - 1) / sync::kTile;
-  int64_t g = (512 + tiles - 1) / tiles;
+  int64_t g = (sync::kTargetGroups + tiles - 1) / tiles;
   if (g > A) g = A;
   if (g > sync::kMaxGroups) g = sync::kMaxGroups;
   if (g < 1) g = 1;
@@ -209,7 +232,7 @@ int sync_groups(int A, int64_t n_search) {
 }
 
 size_t sync_workspace(int A, int64_t n_search) {
-  const int64_t nb = (n_search + 255) / 256;
+  const int64_t nb = (n_search + sync::kRedCand - 1) / sync::kRedCand;
   return (size_t)sync_groups(A, n_search) * n_search * 8 + (size_t)nb * 16;
 }
 
@@ -219,11 +242,11 @@ hipError_t sync_find(const uint32_t* raw, int A, int64_t n_samples, int64_t stri
   const int G = sync_groups(A, n_search);
   const int ag = (A + G - 1) / G;
   const int64_t tiles = (n_search + sync::kTile - 1) / sync::kTile;
-  const int64_t nb = (n_search + 255) / 256;
+  const int64_t nb = (n_search + sync::kRedCand - 1) / sync::kRedCand;
   uint64_t* part = static_cast<uint64_t*>(workspace);
   uint64_t* cv = part + (int64_t)G * n_search;
   int64_t* ci = reinterpret_cast<int64_t*>(cv + nb);
-  const size_t lds = sizeof(uint32_t) * (size_t)(sync::kTile + ch.L + 3);
+  const size_t lds = sizeof(uint32_t) * 4 * (size_t)sync::plane_dwords(ch.L);
   hipLaunchKernelGGL(sync::sync_metric_kernel, dim3((unsigned)tiles, (unsigned)G), dim3(sync::kThreads), lds, st,
                      raw, A, ag, n_samples, stride, ch, n_search, part);
   hipError_t e = hipGetLastError();

@@ -124,7 +124,7 @@ def bench_batch(args):
     t0 = time.time()
     batch.autotune(iq, out, reps=8)
     classes = sorted({c.fft_len for c in bt.configs})
-    chosen = {n: batch.config(n) for n in classes}
+    chosen = {n: batch.config(n) + batch.schedules(n) for n in classes}
     log(f"autotuned in {time.time() - t0:.1f} s: {chosen}")
     for _ in range(args.warmup):
         batch.process(iq, out)
@@ -155,7 +155,10 @@ def bench_batch(args):
            "hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
            "frame_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                                 "max": float(lat.max()), "samples": int(lat.size)},
-           "autotuned": {str(n): {"demod_waves": w, "est_jobs": j} for n, (w, j) in chosen.items()},
+           "autotuned": {str(n): {"demod_waves": w, "est_jobs": j,
+                                  "demod_radices": list(rx.fft_radices(n, sd)),
+                                  "est_radices": list(rx.fft_radices(n, se))}
+                         for n, (w, j, sd, se) in chosen.items()},
            "kernel_hash": kernel_hash()}
     print(json.dumps(rec), flush=True)
 

@@ -193,17 +193,43 @@ size_t rx_batch_workspace_bytes(rx_batch_t batch);
 int rx_batch_process(rx_batch_t batch, const int16_t* iq, float* H, float* xhat, uint8_t* bits,
                      void* workspace, void* hip_stream);
 
-/* Time every launch configuration of every FFT-length class on these buffers
- * (reps timed runs each after one warm-up, the minimum counts): first each
- * class alone, then, class by class from the longest, within the whole batch
- * graph with the other classes as chosen so far; keeps the configuration with
- * the shortest batch.  Synchronous; overwrites the outputs. */
+/* Time the launch configurations of every FFT-length class on these buffers
+ * (reps timed runs each after one warm-up, the minimum counts).  A
+ * configuration is the demod workgroup size, the estimate's jobs per
+ * wavefront and the radix schedule of each kernel's transforms (see
+ * rx_fft_radices).  First each class alone: every shape under every
+ * schedule, the estimate's and the demod's choices made separately; then,
+ * class by class from the longest, within the whole batch graph with the
+ * other classes as chosen so far: every shape with the class's schedules,
+ * then every pair of schedules with the best shape, a choice replaced only
+ * by one more than 1 % faster.  Synchronous; overwrites the outputs. */
 int rx_batch_autotune(rx_batch_t batch, const int16_t* iq, float* H, float* xhat, uint8_t* bits,
                       void* workspace, int32_t reps, void* hip_stream);
 
 /* Configuration in use for the class of FFT length fft_len: wavefronts per
  * demod workgroup and jobs per estimate wavefront. */
 int rx_batch_config(rx_batch_t batch, int32_t fft_len, int32_t* demod_waves, int32_t* est_jobs);
+
+/* Radix schedules in use for the class of FFT length fft_len: of the demod
+ * kernel's transforms and of the estimate kernel's (indices as in
+ * rx_fft_radices).  RX_E_INVALID_ARG if the batch has no such class. */
+int rx_batch_schedules(rx_batch_t batch, int32_t fft_len, int32_t* dem_sched, int32_t* est_sched);
+
+/* Set the configuration of the class of FFT length fft_len instead of tuning
+ * it: demod_waves and est_jobs in {2, 4, 8}, schedules below the count
+ * rx_fft_radices accepts for fft_len.  The batch's current device only;
+ * RX_E_INVALID_ARG for anything else (the configuration is then unchanged).
+ * The next rx_batch_process rebuilds its graph. */
+int rx_batch_set_config(rx_batch_t batch, int32_t fft_len, int32_t demod_waves, int32_t est_jobs,
+                        int32_t dem_sched, int32_t est_sched);
+
+/* Radix schedule `sched` of the fft_len-point transform of the batch kernels
+ * (paper Sec. II-B: the FFT stage): radices[0..2] receive the radix of each
+ * Stockham pass, first pass first, 0 after the last pass (radix 16 first in
+ * every schedule; 512, 1024 and 2048 have two schedules, 16-R-16 and 16-16-R,
+ * the other lengths one).  RX_E_UNSUPPORTED when fft_len has no schedule
+ * `sched`; host only. */
+int rx_fft_radices(int32_t fft_len, int32_t sched, int32_t* radices);
 
 /* Per-frame completion time of the most recent rx_batch_process, in ms after
  * the batch started on the device (device clock); ms has n_frames entries.

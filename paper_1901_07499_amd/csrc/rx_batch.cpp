@@ -8,13 +8,16 @@
 // reset node (clears the queues, stamps the start time) and one two-node
 // branch per class, the branches independent of each other, so one graph
 // launch processes the whole batch.  The autotuner times the launch
-// configurations of every class on the caller's data, first each class alone
-// and then within the whole graph, and keeps the fastest.
+// configurations of every class (workgroup shapes and the FFT's radix
+// schedule, chosen separately for the estimate and demod kernels) on the
+// caller's data, first each class alone and then within the whole graph, and
+// keeps the fastest.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <initializer_list>
 #include <new>
 #include <vector>
 
@@ -29,6 +32,7 @@ struct BatchClass {
   std::vector<int> frames;  // batch indices, in batch order
   int demod_waves = 4;      // tuned launch configuration
   int est_jobs = 4;
+  int dem_sched = 0, est_sched = 0;  // radix schedules of the two kernels' transforms
   int n_est_tiles = 0, n_dem_tiles = 0;
   rx::FrameDesc* d_desc = nullptr;
   int* d_est_map = nullptr;
@@ -89,7 +93,8 @@ void free_all(rx_batch_s* b) {
 // (Re)build the descriptors, tile maps and launch geometry of class c for
 // its current configuration.
 int configure_class(rx_batch_s* b, BatchClass& c) {
-  if (!rx::batch_kernels(c.N, c.max_u, c.demod_waves, c.est_jobs, c.dem, c.est)) return RX_E_UNSUPPORTED;
+  if (!rx::batch_kernels(c.N, c.max_u, c.demod_waves, c.est_jobs, c.dem_sched, c.est_sched, c.dem, c.est))
+    return RX_E_UNSUPPORTED;
   std::vector<rx::FrameDesc> desc;
   std::vector<int> est_map, dem_map;
   // Queue order: frames with more antennas (longer tiles) first, ties in batch
@@ -429,82 +434,111 @@ int rx_batch_autotune(rx_batch_t b, const int16_t* iq, float* H, float* xhat, ui
   }
   drop_graph(b);
   // Pass 1: each class alone, its estimate and demod kernels timed separately
-  // (minimum over the timed runs: robust to interference).
+  // (minimum over the timed runs: robust to interference); the estimate's
+  // jobs and schedule and the demod's workgroup size and schedule are chosen
+  // independently.
   std::vector<float> alone(b->cls.size(), 0.f);
   for (size_t ci = 0; ci < b->cls.size() && st == RX_OK; ci++) {
     BatchClass& c = b->cls[ci];
+    const int n_sched = rx::fft_schedule_count(c.N);
     float best_e = 1e30f, best_d = 1e30f;
-    int best_w = c.demod_waves, best_j = c.est_jobs;
-    for (int w : {2, 4, 8}) {
-      for (int j : {2, 4, 8}) {
-        c.demod_waves = w;
-        c.est_jobs = j;
-        if ((st = configure_class(b, c)) != RX_OK) break;
-        float me = 1e30f, md = 1e30f;
-        for (int r = 0; r <= reps && st == RX_OK; r++) {  // first run is a warm-up
-          float te = 0.f, td = 0.f;
-          st = run_class_timed(b, ci, io, s, e0, e1, e2, &te, &td);
-          if (r > 0) {
-            me = std::min(me, te);
-            md = std::min(md, td);
+    int best_w = c.demod_waves, best_j = c.est_jobs, best_sd = c.dem_sched, best_se = c.est_sched;
+    for (int sc = 0; sc < n_sched && st == RX_OK; sc++) {
+      for (int w : {2, 4, 8}) {
+        for (int j : {2, 4, 8}) {
+          c.demod_waves = w;
+          c.est_jobs = j;
+          c.dem_sched = c.est_sched = sc;
+          if ((st = configure_class(b, c)) != RX_OK) break;
+          float me = 1e30f, md = 1e30f;
+          for (int r = 0; r <= reps && st == RX_OK; r++) {  // first run is a warm-up
+            float te = 0.f, td = 0.f;
+            st = run_class_timed(b, ci, io, s, e0, e1, e2, &te, &td);
+            if (r > 0) {
+              me = std::min(me, te);
+              md = std::min(md, td);
+            }
+          }
+          if (st != RX_OK) break;
+          if (me < best_e) {
+            best_e = me;
+            best_j = j;
+            best_se = sc;
+          }
+          if (md < best_d) {
+            best_d = md;
+            best_w = w;
+            best_sd = sc;
           }
         }
         if (st != RX_OK) break;
-        if (me < best_e) {
-          best_e = me;
-          best_j = j;
-        }
-        if (md < best_d) {
-          best_d = md;
-          best_w = w;
-        }
       }
-      if (st != RX_OK) break;
     }
     c.demod_waves = best_w;
     c.est_jobs = best_j;
+    c.dem_sched = best_sd;
+    c.est_sched = best_se;
     alone[ci] = best_e + best_d;
     if (st == RX_OK) st = configure_class(b, c);
   }
   // Pass 2: the classes share the GPU inside one graph launch, so a class's
   // best configuration alone need not be best in the batch.  Class by class,
-  // longest first, every configuration is timed within the whole graph (the
-  // other classes as chosen so far) and the one with the shortest batch kept;
-  // the incumbent (timed first) is only replaced by a configuration more than
-  // 1 % faster, so timing noise does not flip choices that do not matter.
+  // longest first, configurations are timed within the whole graph (the other
+  // classes as chosen so far): every workgroup shape with the class's
+  // schedules, then every pair of schedules with the best shape.  The
+  // incumbent (timed first) is only replaced by a configuration more than 1 %
+  // faster, so timing noise does not flip choices that do not matter.
   std::vector<size_t> order(b->cls.size());
   for (size_t i = 0; i < order.size(); i++) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return alone[x] > alone[y]; });
+  struct Cfg {
+    int w, j, sd, se;
+    bool operator==(const Cfg& o) const { return w == o.w && j == o.j && sd == o.sd && se == o.se; }
+  };
+  auto time_graph = [&](BatchClass& c, const Cfg& g, float* ms) {
+    c.demod_waves = g.w;
+    c.est_jobs = g.j;
+    c.dem_sched = g.sd;
+    c.est_sched = g.se;
+    int rc = configure_class(b, c);
+    if (rc == RX_OK) rc = build_graph(b, io);
+    float m = 1e30f;
+    for (int r = 0; r <= reps && rc == RX_OK; r++) {  // first run is a warm-up
+      float t = 0.f;
+      if (hipEventRecord(e0, s) != hipSuccess || hipGraphLaunch(b->exec, s) != hipSuccess ||
+          hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&t, e0, e1) != hipSuccess)
+        rc = RX_E_HIP;
+      else if (r > 0)
+        m = std::min(m, t);
+    }
+    *ms = m;
+    return rc;
+  };
   for (size_t oi = 0; oi < order.size() && st == RX_OK && b->cls.size() > 1; oi++) {
     BatchClass& c = b->cls[order[oi]];
+    const int n_sched = rx::fft_schedule_count(c.N);
+    const Cfg inc{c.demod_waves, c.est_jobs, c.dem_sched, c.est_sched};
+    Cfg best_cfg = inc;
     float best = 1e30f;
-    const int inc_w = c.demod_waves, inc_j = c.est_jobs;
-    int best_w = inc_w, best_j = inc_j;
-    const int cand[10][2] = {{inc_w, inc_j}, {2, 2}, {2, 4}, {2, 8}, {4, 2}, {4, 4}, {4, 8}, {8, 2}, {8, 4}, {8, 8}};
-    for (int k = 0; k < 10 && st == RX_OK; k++) {
-      const int w = cand[k][0], j = cand[k][1];
-      if (k > 0 && w == inc_w && j == inc_j) continue;
-      c.demod_waves = w;
-      c.est_jobs = j;
-      if ((st = configure_class(b, c)) != RX_OK || (st = build_graph(b, io)) != RX_OK) break;
-      float m = 1e30f;
-      for (int r = 0; r <= reps && st == RX_OK; r++) {  // first run is a warm-up
-        float t = 0.f;
-        if (hipEventRecord(e0, s) != hipSuccess || hipGraphLaunch(b->exec, s) != hipSuccess ||
-            hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-            hipEventElapsedTime(&t, e0, e1) != hipSuccess)
-          st = RX_E_HIP;
-        else if (r > 0)
-          m = std::min(m, t);
-      }
-      if (st == RX_OK && (k == 0 || m < 0.99f * best)) {
+    if ((st = time_graph(c, inc, &best)) != RX_OK) break;
+    auto consider = [&](const Cfg& g) {
+      if (st != RX_OK || g == best_cfg || g == inc) return;
+      float m = 0.f;
+      if ((st = time_graph(c, g, &m)) == RX_OK && m < 0.99f * best) {
         best = m;
-        best_w = w;
-        best_j = j;
+        best_cfg = g;
       }
-    }
-    c.demod_waves = best_w;
-    c.est_jobs = best_j;
+    };
+    for (int w : {2, 4, 8})
+      for (int j : {2, 4, 8}) consider(Cfg{w, j, inc.sd, inc.se});
+    const Cfg shape = best_cfg;
+    for (int sd = 0; sd < n_sched; sd++)
+      for (int se = 0; se < n_sched; se++) consider(Cfg{shape.w, shape.j, sd, se});
+    c.demod_waves = best_cfg.w;
+    c.est_jobs = best_cfg.j;
+    c.dem_sched = best_cfg.sd;
+    c.est_sched = best_cfg.se;
     if (st == RX_OK) st = configure_class(b, c);
   }
   drop_graph(b);  // rebuilt for the chosen configurations by the next rx_batch_process
@@ -523,6 +557,58 @@ int rx_batch_config(rx_batch_t b, int32_t fft_len, int32_t* demod_waves, int32_t
       return RX_OK;
     }
   return RX_E_INVALID_ARG;
+}
+
+int rx_batch_schedules(rx_batch_t b, int32_t fft_len, int32_t* dem_sched, int32_t* est_sched) {
+  if (!b) return RX_E_INVALID_ARG;
+  for (const auto& c : b->cls)
+    if (c.N == fft_len) {
+      if (dem_sched) *dem_sched = c.dem_sched;
+      if (est_sched) *est_sched = c.est_sched;
+      return RX_OK;
+    }
+  return RX_E_INVALID_ARG;
+}
+
+int rx_batch_set_config(rx_batch_t b, int32_t fft_len, int32_t demod_waves, int32_t est_jobs, int32_t dem_sched,
+                        int32_t est_sched) {
+  if (!b) return RX_E_INVALID_ARG;
+  auto it = std::find_if(b->cls.begin(), b->cls.end(), [fft_len](const BatchClass& c) { return c.N == fft_len; });
+  if (it == b->cls.end()) return RX_E_INVALID_ARG;
+  const auto in = [](int v, std::initializer_list<int> ok) { return std::find(ok.begin(), ok.end(), v) != ok.end(); };
+  const int n_sched = rx::fft_schedule_count(fft_len);
+  if (!in(demod_waves, {2, 4, 8}) || !in(est_jobs, {2, 4, 8}) || dem_sched < 0 || dem_sched >= n_sched ||
+      est_sched < 0 || est_sched >= n_sched)
+    return RX_E_INVALID_ARG;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return RX_E_HIP;
+  if (dev != b->device) return RX_E_INVALID_ARG;
+  BatchClass& c = *it;
+  const int old[4] = {c.demod_waves, c.est_jobs, c.dem_sched, c.est_sched};
+  c.demod_waves = demod_waves;
+  c.est_jobs = est_jobs;
+  c.dem_sched = dem_sched;
+  c.est_sched = est_sched;
+  drop_graph(b);
+  int st = configure_class(b, c);
+  if (st != RX_OK) {
+    c.demod_waves = old[0];
+    c.est_jobs = old[1];
+    c.dem_sched = old[2];
+    c.est_sched = old[3];
+    (void)configure_class(b, c);
+  }
+  return st;
+}
+
+int rx_fft_radices(int32_t fft_len, int32_t sched, int32_t* radices) {
+  if (!radices) return RX_E_INVALID_ARG;
+  const int n = rx::fft_schedule_count(fft_len);
+  if (n == 0 || sched < 0 || sched >= n) return RX_E_UNSUPPORTED;
+  int r[3];
+  rx::fft_schedule_radices(fft_len, sched, r);
+  for (int i = 0; i < 3; i++) radices[i] = r[i];
+  return RX_OK;
 }
 
 int rx_batch_frame_latency(rx_batch_t b, double* ms, void* hip_stream) {

@@ -190,17 +190,30 @@ __device__ __forceinline__ void exchange_fence() {
   else lds_barrier();
 }
 
-// Radix schedule per N: the first pass is always radix 16 (16 points of one
-// transform per lane, loaded straight from memory); later radices are chosen
-// to keep the number of distinct twiddles per lane small.
+// Radix schedules per N: the first pass is always radix 16 (16 points of one
+// transform per lane, loaded straight from memory).  Schedule 0 puts the
+// small radix in the middle (its pass has few distinct twiddles per lane and
+// the last pass is a full radix 16); schedule 1, for the three-pass lengths,
+// puts it last (16 twiddles of the middle pass per lane instead, a smaller
+// last-pass table).  Lengths with two passes have schedule 0 only.
 template <int N>
-struct Radices;
-template <> struct Radices<64>   { static constexpr int R1 = 16, R2 = 4, R3 = 0; };
-template <> struct Radices<128>  { static constexpr int R1 = 16, R2 = 8, R3 = 0; };
-template <> struct Radices<256>  { static constexpr int R1 = 16, R2 = 16, R3 = 0; };
-template <> struct Radices<512>  { static constexpr int R1 = 16, R2 = 2, R3 = 16; };
-template <> struct Radices<1024> { static constexpr int R1 = 16, R2 = 4, R3 = 16; };
-template <> struct Radices<2048> { static constexpr int R1 = 16, R2 = 8, R3 = 16; };
+struct Radices0;
+template <> struct Radices0<64>   { static constexpr int R1 = 16, R2 = 4, R3 = 0; };
+template <> struct Radices0<128>  { static constexpr int R1 = 16, R2 = 8, R3 = 0; };
+template <> struct Radices0<256>  { static constexpr int R1 = 16, R2 = 16, R3 = 0; };
+template <> struct Radices0<512>  { static constexpr int R1 = 16, R2 = 2, R3 = 16; };
+template <> struct Radices0<1024> { static constexpr int R1 = 16, R2 = 4, R3 = 16; };
+template <> struct Radices0<2048> { static constexpr int R1 = 16, R2 = 8, R3 = 16; };
+
+template <int N, int S = 0>
+struct Radices : Radices0<N> {
+  static_assert(S == 0 || Radices0<N>::R3 > 0, "schedule 1 exists for three-pass lengths only");
+  static constexpr int R2 = S == 0 ? Radices0<N>::R2 : Radices0<N>::R3;
+  static constexpr int R3 = S == 0 ? Radices0<N>::R3 : Radices0<N>::R2;
+};
+
+// Number of radix schedules of length N.
+__host__ __device__ constexpr int fft_schedules(int N) { return N >= 512 ? 2 : 1; }
 
 // Twiddles of one pass (radix R after stride NS) for this lane's butterflies
 // j_m = li + L*m: element r of butterfly m is multiplied by
@@ -255,9 +268,10 @@ struct LdsTwiddles {
 #define RX_LAST_TWIDDLES_IN_LDS 1
 #endif
 
-template <int N>
+template <int N, int S = 0>
 struct FftTwiddles {
-  using Rd = Radices<N>;
+  static constexpr int kSchedule = S;
+  using Rd = Radices<N, S>;
   static constexpr bool kLdsLast = RX_LAST_TWIDDLES_IN_LDS && Rd::R3 > 0;
   using P3Regs = PassTwiddles<N, Rd::R3, Rd::R1 * Rd::R2>;
   using P3Lds = LdsTwiddles<N, Rd::R3, Rd::R1 * Rd::R2>;
@@ -334,15 +348,16 @@ __device__ __forceinline__ void stockham_pass(float2 (&v)[C][FftShape<N>::P], fl
 // q = m + NB*r, so the lane holds bins k = li + L*q, q = 0..P-1, in
 // v[c][Spectrum<N>::reg(q)].  buf[c] is left holding the previous pass's
 // data; the caller fences before writing it again.
-template <int N>
+template <int N, int S = 0>
 struct Spectrum {
-  using Rd = Radices<N>;
+  using Rd = Radices<N, S>;
   static constexpr int R = Rd::R3 > 0 ? Rd::R3 : Rd::R2;  // last radix
   static constexpr int NB = FftShape<N>::P / R;
   static constexpr int reg(int q) { return (q % NB) * R + q / NB; }
 };
 
-// First pass only (inputs in registers, output to LDS).
+// First pass only (inputs in registers, output to LDS); radix 16 in every
+// schedule.
 template <int N, int C>
 __device__ __forceinline__ void fft_first_pass(float2 (&v)[C][FftShape<N>::P], float2* const (&buf)[C], int li) {
   using Rd = Radices<N>;
@@ -350,11 +365,12 @@ __device__ __forceinline__ void fft_first_pass(float2 (&v)[C][FftShape<N>::P], f
   stockham_pass<N, Rd::R1, 1, true, false, C>(v, buf, li, none);
 }
 
-// The passes after the first; the spectrum ends in v.
-template <int N, int C>
+// The passes after the first; the spectrum ends in v.  The schedule comes
+// with the twiddles' type.
+template <int N, int C, int S>
 __device__ __forceinline__ void fft_rest(float2 (&v)[C][FftShape<N>::P], float2* const (&buf)[C], int li,
-                                         const FftTwiddles<N>& tw) {
-  using Rd = Radices<N>;
+                                         const FftTwiddles<N, S>& tw) {
+  using Rd = Radices<N, S>;
   if constexpr (Rd::R3 > 0) {
     stockham_pass<N, Rd::R2, Rd::R1, false, false, C>(v, buf, li, tw.p2);
     stockham_pass<N, Rd::R3, Rd::R1 * Rd::R2, false, true, C>(v, buf, li, tw.p3);
@@ -363,17 +379,17 @@ __device__ __forceinline__ void fft_rest(float2 (&v)[C][FftShape<N>::P], float2*
   }
 }
 
-template <int N, int C>
+template <int N, int C, int S>
 __device__ __forceinline__ void fft_in_regs(float2 (&v)[C][FftShape<N>::P], float2* const (&buf)[C], int li,
-                                            const FftTwiddles<N>& tw) {
+                                            const FftTwiddles<N, S>& tw) {
   fft_first_pass<N, C>(v, buf, li);
   fft_rest<N, C>(v, buf, li, tw);
 }
 
 // Single-transform form.
-template <int N>
+template <int N, int S>
 __device__ __forceinline__ void fft_in_regs(float2 (&v)[FftShape<N>::P], float2* buf, int li,
-                                            const FftTwiddles<N>& tw) {
+                                            const FftTwiddles<N, S>& tw) {
   float2 vv[1][FftShape<N>::P];
 #pragma unroll
   for (int i = 0; i < FftShape<N>::P; i++) vv[0][i] = v[i];

@@ -104,16 +104,16 @@ struct EstLane {
 // H row out (hrow null: nothing stored).  With a comb pilot (every ps-th used
 // subcarrier) the LS values go to the transform's LDS slot and every
 // subcarrier is interpolated from them.  Ends with an exchange fence.
-template <int N>
+template <int N, int S>
 __device__ __forceinline__ void estimate_job(float2 (&v)[FftShape<N>::P], const EstLane<N>& el, float2* buf, int li,
-                                             const FftTwiddles<N>& twr, float2* __restrict__ hrow, int U, int ps) {
+                                             const FftTwiddles<N, S>& twr, float2* __restrict__ hrow, int U, int ps) {
   using Sh = FftShape<N>;
   fft_in_regs<N>(v, buf, li, twr);
   if (ps <= 1) {
     if (hrow) {
 #pragma unroll
       for (int q = 0; q < Sh::P; q++)
-        if (el.dq[q] >= 0) hrow[el.dq[q]] = cmul(v[Spectrum<N>::reg(q)], el.pq[q]);
+        if (el.dq[q] >= 0) hrow[el.dq[q]] = cmul(v[Spectrum<N, S>::reg(q)], el.pq[q]);
     }
   } else {
     // comb: LS on the pilot subcarriers into this transform's LDS slot (the
@@ -121,7 +121,7 @@ __device__ __forceinline__ void estimate_job(float2 (&v)[FftShape<N>::P], const 
     exchange_fence<N>();
 #pragma unroll
     for (int q = 0; q < Sh::P; q++)
-      if (el.dq[q] >= 0 && el.dq[q] % ps == 0) buf[el.dq[q] / ps] = cmul(v[Spectrum<N>::reg(q)], el.pq[q]);
+      if (el.dq[q] >= 0 && el.dq[q] % ps == 0) buf[el.dq[q] / ps] = cmul(v[Spectrum<N, S>::reg(q)], el.pq[q]);
     exchange_fence<N>();
     if (hrow)
       for (int d = li; d < U; d += Sh::L) hrow[d] = comb_value(buf, d, U, ps);
@@ -136,10 +136,10 @@ __device__ __forceinline__ void estimate_job(float2 (&v)[FftShape<N>::P], const 
 // uniform over whoever shares an exchange fence (the wavefront, or the
 // workgroup for two-wavefront transforms): a transform whose antenna is past
 // A transforms a valid antenna's samples and stores nothing.
-template <int N, int W, int J>
+template <int N, int W, int J, int S>
 __device__ __forceinline__ void estimate_tile(const uint32_t* __restrict__ slot_iq, int A, int CP, int U,
                                               const float2* __restrict__ pf, float2* __restrict__ Hs,
-                                              int a_wg, float2* lds, const FftTwiddles<N>& twr, int ps) {
+                                              int a_wg, float2* lds, const FftTwiddles<N, S>& twr, int ps) {
   using Sh = FftShape<N>;
   constexpr int TPW = transforms_per_group<N, W>();
   const int li = threadIdx.x % Sh::L, ts = threadIdx.x / Sh::L;
@@ -170,10 +170,10 @@ __device__ __forceinline__ void estimate_tile(const uint32_t* __restrict__ slot_
 
 // Fill the last-pass twiddle table (once per workgroup) and load this lane's
 // twiddles.  Contains a workgroup barrier when the table is used.
-template <int N>
-__device__ __forceinline__ void tile_setup(FftTwiddles<N>& twr, float2* twtab, const float2* __restrict__ tw) {
-  if constexpr (FftTwiddles<N>::kLdsLast) {
-    FftTwiddles<N>::P3Lds::fill(twtab, tw, threadIdx.x, blockDim.x);
+template <int N, int S>
+__device__ __forceinline__ void tile_setup(FftTwiddles<N, S>& twr, float2* twtab, const float2* __restrict__ tw) {
+  if constexpr (FftTwiddles<N, S>::kLdsLast) {
+    FftTwiddles<N, S>::P3Lds::fill(twtab, tw, threadIdx.x, blockDim.x);
     __syncthreads();
   }
   twr.load(tw, threadIdx.x % FftShape<N>::L, twtab);
@@ -260,8 +260,8 @@ struct SlotView {
 // Demodulate data symbol t of one slot with the W wavefronts of the
 // workgroup.  Uses the dynamic LDS `lds` (exchange buffers, then the
 // reduction rows); every thread of the workgroup must call it.
-template <int N, int QH, int W, bool ZF>
-__device__ __forceinline__ void demod_tile(const SlotView& sv, int t, float2* lds, const FftTwiddles<N>& twr) {
+template <int N, int QH, int W, bool ZF, int S>
+__device__ __forceinline__ void demod_tile(const SlotView& sv, int t, float2* lds, const FftTwiddles<N, S>& twr) {
   using Sh = FftShape<N>;
   constexpr int NI = 2 * QH;  // spectrum registers that can hold a used subcarrier
   static_assert(NI <= Sh::P, "window wider than the lane's spectrum");
@@ -389,7 +389,7 @@ __device__ __forceinline__ void demod_tile(const SlotView& sv, int t, float2* ld
 #pragma unroll
       for (int i = 0; i < NI; i++) {
         const int q = i < QH ? i : Sh::P - NI + i;
-        const float2 y = v[c][Spectrum<N>::reg(q)];
+        const float2 y = v[c][Spectrum<N, S>::reg(q)];
         const float2 hh = h[c][i];  // zero for antennas past A
         if constexpr (ZF) {
           const float2 w = make_float2(hh.x * g[i], -hh.y * g[i]);  // conj(h) / g
@@ -539,15 +539,16 @@ __device__ __forceinline__ int next_tile(int* queue, int n_tiles, const int* til
   return tile;
 }
 
-template <int N, int W, int J>
+// Batch kernels: S is the radix schedule of the class's transforms.
+template <int N, int W, int J, int S>
 __global__ __launch_bounds__(64 * W) void batch_estimate_kernel(const FrameDesc* __restrict__ fd,
                                                                 const int* __restrict__ tile_frame, int n_tiles,
                                                                 BatchIo io, const float2* __restrict__ tw,
                                                                 int* queue) {
   extern __shared__ float2 lds[];
-  __shared__ float2 twtab[FftTwiddles<N>::kLdsFloat2 > 0 ? FftTwiddles<N>::kLdsFloat2 : 1];
+  __shared__ float2 twtab[FftTwiddles<N, S>::kLdsFloat2 > 0 ? FftTwiddles<N, S>::kLdsFloat2 : 1];
   __shared__ int tile_sh, frame_sh;
-  FftTwiddles<N> twr;
+  FftTwiddles<N, S> twr;
   tile_setup<N>(twr, twtab, tw);
   for (;;) {
     int frame;
@@ -559,16 +560,16 @@ __global__ __launch_bounds__(64 * W) void batch_estimate_kernel(const FrameDesc*
   }
 }
 
-template <int N, int QH, int W>
+template <int N, int QH, int W, int S>
 __global__ __launch_bounds__(64 * W) void batch_demod_kernel(const FrameDesc* __restrict__ fd,
                                                              const int* __restrict__ tile_frame, int n_tiles,
                                                              BatchIo io, const float2* __restrict__ tw,
                                                              int* queue, int* done_count,
                                                              unsigned long long* done_time) {
   extern __shared__ float2 lds[];
-  __shared__ float2 twtab[FftTwiddles<N>::kLdsFloat2 > 0 ? FftTwiddles<N>::kLdsFloat2 : 1];
+  __shared__ float2 twtab[FftTwiddles<N, S>::kLdsFloat2 > 0 ? FftTwiddles<N, S>::kLdsFloat2 : 1];
   __shared__ int tile_sh, frame_sh;
-  FftTwiddles<N> twr;
+  FftTwiddles<N, S> twr;
   tile_setup<N>(twr, twtab, tw);
   for (;;) {
     int frame;
@@ -814,63 +815,113 @@ hipError_t launch_fft(const LaunchArgs& la, float2* Y) {
 
 // ------------------------------------------------------------------ batch kernel lookup
 namespace {
-template <int N, int QH, int W>
+template <int N, int QH, int W, int S>
 void demod_entry(BatchKernel& k) {
-  k.func = reinterpret_cast<const void*>(batch_demod_kernel<N, QH, W>);
+  k.func = reinterpret_cast<const void*>(batch_demod_kernel<N, QH, W, S>);
   k.block = 64 * W;
 }
-template <int N, int W, int J>
+template <int N, int W, int J, int S>
 void est_entry(BatchKernel& k) {
-  k.func = reinterpret_cast<const void*>(batch_estimate_kernel<N, W, J>);
+  k.func = reinterpret_cast<const void*>(batch_estimate_kernel<N, W, J, S>);
   k.block = 64 * W;
 }
-template <int N, int W>
+template <int N, int W, int S>
 bool demod_qh_pick(int need, BatchKernel& k) {
   static_assert(FftShape<N>::P == 16, "tiers assume 16 points per lane");
-  if (need <= 5) { demod_entry<N, 5, W>(k); return true; }
-  if (need <= 8) { demod_entry<N, 8, W>(k); return true; }
+  if (need <= 5) { demod_entry<N, 5, W, S>(k); return true; }
+  if (need <= 8) { demod_entry<N, 8, W, S>(k); return true; }
   return false;
 }
 // Transforms per workgroup of w wavefronts (w a multiple of the wavefronts per transform).
 template <int N>
 int tpw(int w) { return 64 * w / FftShape<N>::L; }
-template <int N>
-bool batch_pick_n(int max_u, int demod_waves, int est_jobs, BatchKernel& dem, BatchKernel& est) {
+template <int N, int S>
+bool dem_pick(int max_u, int demod_waves, BatchKernel& dem) {
   constexpr int L = FftShape<N>::L;
   const int need = (max_u / 2 + 1 + L - 1) / L;
   bool ok = false;
   switch (demod_waves) {
-    case 2: ok = demod_qh_pick<N, 2>(need, dem); break;
-    case 4: ok = demod_qh_pick<N, 4>(need, dem); break;
-    case 8: ok = demod_qh_pick<N, 8>(need, dem); break;
+    case 2: ok = demod_qh_pick<N, 2, S>(need, dem); break;
+    case 4: ok = demod_qh_pick<N, 4, S>(need, dem); break;
+    case 8: ok = demod_qh_pick<N, 8, S>(need, dem); break;
     default: return false;
   }
   if (!ok) return false;
   // LDS of the demod tile: exchange buffers, or the reduction rows if larger
   dem.lds_fft = (size_t)tpw<N>(demod_waves) * Lds<N>::kSlot * sizeof(float2);
   dem.lds_per_u = (size_t)tpw<N>(demod_waves) * (sizeof(float2) + sizeof(float));
+  dem.ants_per_tile = 0;
+  return true;
+}
+template <int N, int S>
+bool est_pick(int est_jobs, BatchKernel& est) {
   switch (est_jobs) {
-    case 2: est_entry<N, 4, 2>(est); break;
-    case 4: est_entry<N, 4, 4>(est); break;
-    case 8: est_entry<N, 4, 8>(est); break;
+    case 2: est_entry<N, 4, 2, S>(est); break;
+    case 4: est_entry<N, 4, 4, S>(est); break;
+    case 8: est_entry<N, 4, 8, S>(est); break;
     default: return false;
   }
   est.lds_fft = (size_t)tpw<N>(4) * Lds<N>::kSlot * sizeof(float2);
   est.lds_per_u = 0;
   est.ants_per_tile = tpw<N>(4) * est_jobs;
-  dem.ants_per_tile = 0;
   return true;
+}
+template <int N>
+bool batch_pick_n(int max_u, int demod_waves, int est_jobs, int dem_sched, int est_sched, BatchKernel& dem,
+                  BatchKernel& est) {
+  bool ok_d = false, ok_e = false;
+  if (dem_sched == 0) ok_d = dem_pick<N, 0>(max_u, demod_waves, dem);
+  if (est_sched == 0) ok_e = est_pick<N, 0>(est_jobs, est);
+  if constexpr (fft_schedules(N) > 1) {
+    if (dem_sched == 1) ok_d = dem_pick<N, 1>(max_u, demod_waves, dem);
+    if (est_sched == 1) ok_e = est_pick<N, 1>(est_jobs, est);
+  }
+  return ok_d && ok_e;
 }
 }  // namespace
 
-bool batch_kernels(int N, int max_u, int demod_waves, int est_jobs, BatchKernel& dem, BatchKernel& est) {
+int fft_schedule_count(int N) {
   switch (N) {
-    case 64: return batch_pick_n<64>(max_u, demod_waves, est_jobs, dem, est);
-    case 128: return batch_pick_n<128>(max_u, demod_waves, est_jobs, dem, est);
-    case 256: return batch_pick_n<256>(max_u, demod_waves, est_jobs, dem, est);
-    case 512: return batch_pick_n<512>(max_u, demod_waves, est_jobs, dem, est);
-    case 1024: return batch_pick_n<1024>(max_u, demod_waves, est_jobs, dem, est);
-    case 2048: return batch_pick_n<2048>(max_u, demod_waves, est_jobs, dem, est);
+    case 64: case 128: case 256: case 512: case 1024: case 2048: return fft_schedules(N);
+    default: return 0;
+  }
+}
+
+namespace {
+template <int N>
+void radices_of(int sched, int radices[3]) {
+  if (sched == 0) {
+    radices[0] = Radices<N, 0>::R1; radices[1] = Radices<N, 0>::R2; radices[2] = Radices<N, 0>::R3;
+  } else if constexpr (fft_schedules(N) > 1) {
+    if (sched == 1) {
+      radices[0] = Radices<N, 1>::R1; radices[1] = Radices<N, 1>::R2; radices[2] = Radices<N, 1>::R3;
+    }
+  }
+}
+}  // namespace
+
+void fft_schedule_radices(int N, int sched, int radices[3]) {
+  radices[0] = radices[1] = radices[2] = 0;
+  switch (N) {
+    case 64: radices_of<64>(sched, radices); break;
+    case 128: radices_of<128>(sched, radices); break;
+    case 256: radices_of<256>(sched, radices); break;
+    case 512: radices_of<512>(sched, radices); break;
+    case 1024: radices_of<1024>(sched, radices); break;
+    case 2048: radices_of<2048>(sched, radices); break;
+    default: break;
+  }
+}
+
+bool batch_kernels(int N, int max_u, int demod_waves, int est_jobs, int dem_sched, int est_sched, BatchKernel& dem,
+                   BatchKernel& est) {
+  switch (N) {
+    case 64: return batch_pick_n<64>(max_u, demod_waves, est_jobs, dem_sched, est_sched, dem, est);
+    case 128: return batch_pick_n<128>(max_u, demod_waves, est_jobs, dem_sched, est_sched, dem, est);
+    case 256: return batch_pick_n<256>(max_u, demod_waves, est_jobs, dem_sched, est_sched, dem, est);
+    case 512: return batch_pick_n<512>(max_u, demod_waves, est_jobs, dem_sched, est_sched, dem, est);
+    case 1024: return batch_pick_n<1024>(max_u, demod_waves, est_jobs, dem_sched, est_sched, dem, est);
+    case 2048: return batch_pick_n<2048>(max_u, demod_waves, est_jobs, dem_sched, est_sched, dem, est);
     default: return false;
   }
 }

@@ -59,9 +59,16 @@ struct BatchKernel {
 };
 
 // Kernels for FFT length N whose frames have at most max_u used subcarriers,
-// with demod_waves in {2,4,8} wavefronts per demod workgroup and est_jobs in
-// {2,4,8} jobs per estimate wavefront.  False if unsupported.
-bool batch_kernels(int N, int max_u, int demod_waves, int est_jobs, BatchKernel& dem, BatchKernel& est);
+// with demod_waves in {2,4,8} wavefronts per demod workgroup, est_jobs in
+// {2,4,8} jobs per estimate wavefront and radix schedules dem_sched and
+// est_sched (below fft_schedule_count(N)).  False if unsupported.
+bool batch_kernels(int N, int max_u, int demod_waves, int est_jobs, int dem_sched, int est_sched, BatchKernel& dem,
+                   BatchKernel& est);
+// Radix schedules of the N-point transform (0 if N is unsupported), and the
+// radices of schedule sched, first pass first (0 after the last pass; all
+// zero if there is no such schedule).
+int fft_schedule_count(int N);
+void fft_schedule_radices(int N, int sched, int radices[3]);
 const void* batch_reset_func();
 
 // ---- learned refinement of the channel estimate (rx_denoise.hip)

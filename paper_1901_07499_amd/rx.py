@@ -26,7 +26,8 @@ FFT_MODES = {"f32": 0, "f16": 1, "bf16": 2, "f16_split": 3, "bf16_split": 4}
 EXPORTS = ("rx_params_check", "rx_plan_create", "rx_plan_destroy", "rx_workspace_bytes", "rx_estimate",
            "rx_demod", "rx_process_frame", "rx_debug_fft", "rx_status_string",
            "rx_batch_create", "rx_batch_destroy", "rx_batch_layout", "rx_batch_workspace_bytes",
-           "rx_batch_process", "rx_batch_autotune", "rx_batch_config", "rx_batch_frame_latency",
+           "rx_batch_process", "rx_batch_autotune", "rx_batch_config", "rx_batch_schedules", "rx_batch_set_config",
+           "rx_fft_radices", "rx_batch_frame_latency",
            "rx_dn_create", "rx_dn_destroy", "rx_dn_load", "rx_dn_apply", "rx_dn_workspace_bytes", "rx_dn_grad",
            "rx_dn_train_step", "rx_dn_generate", "rx_sync_workspace_bytes", "rx_sync_find", "rx_sync_extract")
 RX_DN_PARAMS = 15330
@@ -86,6 +87,10 @@ def _load() -> ctypes.CDLL:
     lib.rx_batch_process.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.rx_batch_autotune.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_int32, vp]
     lib.rx_batch_config.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    lib.rx_batch_schedules.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32)]
+    lib.rx_batch_set_config.argtypes = [vp] + [ctypes.c_int32] * 5
+    lib.rx_fft_radices.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     lib.rx_batch_frame_latency.argtypes = [vp, ctypes.POINTER(ctypes.c_double), vp]
     f32 = ctypes.c_float
     lib.rx_dn_create.argtypes = [ctypes.c_int32, ctypes.POINTER(vp)]
@@ -180,6 +185,26 @@ def rx_batch_autotune(batch, iq, H, xhat, bits, workspace, reps, stream) -> int:
 
 def rx_batch_config(batch, fft_len, demod_waves, est_jobs) -> int:
     return _lib.rx_batch_config(batch, fft_len, demod_waves, est_jobs)
+
+
+def rx_batch_schedules(batch, fft_len, dem_sched, est_sched) -> int:
+    return _lib.rx_batch_schedules(batch, fft_len, dem_sched, est_sched)
+
+
+def rx_batch_set_config(batch, fft_len, demod_waves, est_jobs, dem_sched, est_sched) -> int:
+    return _lib.rx_batch_set_config(batch, fft_len, demod_waves, est_jobs, dem_sched, est_sched)
+
+
+def rx_fft_radices(fft_len, sched, radices) -> int:
+    return _lib.rx_fft_radices(fft_len, sched, radices)
+
+
+def fft_radices(fft_len: int, sched: int) -> Optional[Tuple[int, ...]]:
+    """Radices of schedule ``sched`` of the fft_len-point transform, first pass first; None if there is none."""
+    r = (ctypes.c_int32 * 3)()
+    if rx_fft_radices(fft_len, sched, r) != RX_OK:
+        return None
+    return tuple(v for v in r[:] if v)
 
 
 def rx_batch_frame_latency(batch, ms, stream) -> int:
@@ -438,6 +463,19 @@ class Batch:
         if st != RX_OK:
             raise RxError(st, "rx_batch_config")
         return w.value, j.value
+
+    def schedules(self, fft_len: int):
+        """(demod, estimate) radix schedule indices of the class of length fft_len."""
+        d, e = ctypes.c_int32(), ctypes.c_int32()
+        st = rx_batch_schedules(self._b, fft_len, ctypes.byref(d), ctypes.byref(e))
+        if st != RX_OK:
+            raise RxError(st, "rx_batch_schedules")
+        return d.value, e.value
+
+    def set_config(self, fft_len: int, demod_waves: int, est_jobs: int, dem_sched: int = 0, est_sched: int = 0):
+        st = rx_batch_set_config(self._b, fft_len, demod_waves, est_jobs, dem_sched, est_sched)
+        if st != RX_OK:
+            raise RxError(st, "rx_batch_set_config")
 
     def frame_latency_ms(self):
         import torch

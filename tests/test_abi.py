@@ -135,3 +135,31 @@ def test_batch_create_validates_before_touching_the_gpu():
     assert rx.rx_batch_destroy(None) == rx.RX_OK
     assert rx.rx_batch_workspace_bytes(None) == 0
     assert rx.rx_batch_process(None, 16, 16, 16, 16, None, None) == rx.RX_E_INVALID_ARG
+
+
+@pytest.mark.parametrize("n", [64, 128, 256, 512, 1024, 2048])
+def test_fft_radix_schedules_factor_the_length(n):
+    # every schedule is a Stockham plan of the n-point DFT: radix 16 first,
+    # the radices multiply to n; the three-pass lengths have a second
+    # schedule with the last two radices swapped
+    scheds = []
+    for s in range(4):
+        r = rx.fft_radices(n, s)
+        if r is None:
+            break
+        scheds.append(r)
+    assert rx.fft_radices(n, len(scheds)) is None and rx.fft_radices(n, -1) is None
+    assert len(scheds) == (2 if n >= 512 else 1)
+    for r in scheds:
+        assert r[0] == 16 and int(np.prod(r)) == n and all(v in (2, 4, 8, 16) for v in r)
+    if len(scheds) == 2:
+        assert scheds[1] == (scheds[0][0], scheds[0][2], scheds[0][1]) and scheds[0] != scheds[1]
+
+
+def test_fft_radices_and_batch_config_reject_bad_arguments():
+    r = (ctypes.c_int32 * 3)()
+    assert rx.rx_fft_radices(1000, 0, r) == rx.RX_E_UNSUPPORTED
+    assert rx.rx_fft_radices(1024, 0, None) == rx.RX_E_INVALID_ARG
+    d, e = ctypes.c_int32(), ctypes.c_int32()
+    assert rx.rx_batch_schedules(None, 1024, ctypes.byref(d), ctypes.byref(e)) == rx.RX_E_INVALID_ARG
+    assert rx.rx_batch_set_config(None, 1024, 4, 4, 0, 0) == rx.RX_E_INVALID_ARG

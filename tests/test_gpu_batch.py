@@ -23,13 +23,13 @@ def _say(*a):
     print("[case]", *a, flush=True)
 
 
-def _check_frames(batch, bt, H, x, b):
+def _check_frames(batch, bt, H, x, b, refs=None):
     Hc = H.cpu().numpy().astype(np.float64)
     xc = x.cpu().numpy().astype(np.float64)
     bc = b.cpu().numpy()
     for i, fr in enumerate(bt.frames):
         c = fr.cfg
-        ref = oracle.run_config(fr)
+        ref = refs[i] if refs is not None else oracle.run_config(fr)
         Hi = Hc[batch.h_off[i]:batch.h_off[i + 1]].reshape(1, c.n_ant, c.n_used, 2)
         xi = xc[batch.x_off[i]:batch.x_off[i + 1]].reshape(1, c.n_sym - 1, c.n_used, 2)
         bi = bc[batch.b_off[i]:batch.b_off[i + 1]].reshape(1, c.n_sym - 1, -1)
@@ -65,6 +65,8 @@ def test_batch_autotune_then_graph_replays(rx):
     for n in sorted({c.fft_len for c in bt.configs}):
         w, j = batch.config(n)
         assert w in (2, 4, 8) and j in (2, 4, 8)
+        sd, se = batch.schedules(n)
+        assert rx.fft_radices(n, sd) is not None and rx.fft_radices(n, se) is not None
     x_prev = None
     for rep in range(3):                      # replays of the same graph, eager work between them
         out[1].fill_(float("nan"))
@@ -74,6 +76,34 @@ def test_batch_autotune_then_graph_replays(rx):
         if x_prev is not None:
             assert torch.equal(out[1], x_prev)
         x_prev = out[1].clone()
+
+
+@pytest.mark.parametrize("sched", [(1, 1), (1, 0), (0, 1)])
+def test_batch_forced_radix_schedules_match_oracle(rx, sched):
+    # each radix schedule of each kernel, on every length that has two, and
+    # the demod at every workgroup size; lengths with one schedule keep it
+    sd, se = sched
+    _say("batch schedules", sched, 12, 34)
+    bt, batch, iq = _make(rx, 12, 34, antennas=(3, 17, 40), fft_lens=(256, 512, 1024, 2048))
+    lens = sorted({c.fft_len for c in bt.configs})
+    assert {512, 1024, 2048} <= set(lens)
+    out = batch.outputs(iq.device)
+    refs = [oracle.run_config(fr) for fr in bt.frames]
+    for w, j in ((2, 8), (4, 2), (8, 4)):
+        for n in lens:
+            two = rx.fft_radices(n, 1) is not None
+            batch.set_config(n, w, j, sd if two else 0, se if two else 0)
+            assert batch.config(n) == (w, j)
+            assert batch.schedules(n) == ((sd, se) if two else (0, 0))
+        out[1].fill_(float("nan"))
+        batch.process(iq, out)
+        torch.cuda.synchronize()
+        _check_frames(batch, bt, *out[:3], refs=refs)
+    with pytest.raises(rx.RxError):
+        batch.set_config(256, 4, 4, 1, 0)            # 256 has one schedule
+    with pytest.raises(rx.RxError):
+        batch.set_config(1024, 3, 4, 0, 0)
+    assert batch.schedules(256) == (0, 0) and batch.config(1024) == (8, 4)
 
 
 def test_batch_new_buffers_and_workspace(rx):

@@ -264,15 +264,14 @@ struct LdsTwiddles {
   __device__ __forceinline__ float2 get(int m, int r) const { return tab[((kShared ? 0 : m) * (R - 1) + r - 1) * L + li]; }
 };
 
-#ifndef RX_LAST_TWIDDLES_IN_LDS
-#define RX_LAST_TWIDDLES_IN_LDS 1
-#endif
-
-template <int N, int S = 0>
+// Twiddles of the passes after the first.  With LDS_LAST the last pass of a
+// three-pass schedule reads its twiddles from a per-workgroup LDS table
+// (fewer VGPRs); otherwise they are held in VGPRs (no LDS reads).
+template <int N, int S = 0, bool LDS_LAST = true>
 struct FftTwiddles {
   static constexpr int kSchedule = S;
   using Rd = Radices<N, S>;
-  static constexpr bool kLdsLast = RX_LAST_TWIDDLES_IN_LDS && Rd::R3 > 0;
+  static constexpr bool kLdsLast = LDS_LAST && Rd::R3 > 0;
   using P3Regs = PassTwiddles<N, Rd::R3, Rd::R1 * Rd::R2>;
   using P3Lds = LdsTwiddles<N, Rd::R3, Rd::R1 * Rd::R2>;
   static constexpr int kLdsFloat2 = kLdsLast ? P3Lds::kCount : 0;  // LDS table size
@@ -367,9 +366,9 @@ __device__ __forceinline__ void fft_first_pass(float2 (&v)[C][FftShape<N>::P], f
 
 // The passes after the first; the spectrum ends in v.  The schedule comes
 // with the twiddles' type.
-template <int N, int C, int S>
+template <int N, int C, int S, bool LL>
 __device__ __forceinline__ void fft_rest(float2 (&v)[C][FftShape<N>::P], float2* const (&buf)[C], int li,
-                                         const FftTwiddles<N, S>& tw) {
+                                         const FftTwiddles<N, S, LL>& tw) {
   using Rd = Radices<N, S>;
   if constexpr (Rd::R3 > 0) {
     stockham_pass<N, Rd::R2, Rd::R1, false, false, C>(v, buf, li, tw.p2);
@@ -379,17 +378,17 @@ __device__ __forceinline__ void fft_rest(float2 (&v)[C][FftShape<N>::P], float2*
   }
 }
 
-template <int N, int C, int S>
+template <int N, int C, int S, bool LL>
 __device__ __forceinline__ void fft_in_regs(float2 (&v)[C][FftShape<N>::P], float2* const (&buf)[C], int li,
-                                            const FftTwiddles<N, S>& tw) {
+                                            const FftTwiddles<N, S, LL>& tw) {
   fft_first_pass<N, C>(v, buf, li);
   fft_rest<N, C>(v, buf, li, tw);
 }
 
 // Single-transform form.
-template <int N, int S>
+template <int N, int S, bool LL>
 __device__ __forceinline__ void fft_in_regs(float2 (&v)[FftShape<N>::P], float2* buf, int li,
-                                            const FftTwiddles<N, S>& tw) {
+                                            const FftTwiddles<N, S, LL>& tw) {
   float2 vv[1][FftShape<N>::P];
 #pragma unroll
   for (int i = 0; i < FftShape<N>::P; i++) vv[0][i] = v[i];

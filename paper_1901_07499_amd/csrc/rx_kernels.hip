@@ -104,9 +104,9 @@ struct EstLane {
 // H row out (hrow null: nothing stored).  With a comb pilot (every ps-th used
 // subcarrier) the LS values go to the transform's LDS slot and every
 // subcarrier is interpolated from them.  Ends with an exchange fence.
-template <int N, int S>
+template <int N, int S, bool LL>
 __device__ __forceinline__ void estimate_job(float2 (&v)[FftShape<N>::P], const EstLane<N>& el, float2* buf, int li,
-                                             const FftTwiddles<N, S>& twr, float2* __restrict__ hrow, int U, int ps) {
+                                             const FftTwiddles<N, S, LL>& twr, float2* __restrict__ hrow, int U, int ps) {
   using Sh = FftShape<N>;
   fft_in_regs<N>(v, buf, li, twr);
   if (ps <= 1) {
@@ -136,10 +136,10 @@ __device__ __forceinline__ void estimate_job(float2 (&v)[FftShape<N>::P], const 
 // uniform over whoever shares an exchange fence (the wavefront, or the
 // workgroup for two-wavefront transforms): a transform whose antenna is past
 // A transforms a valid antenna's samples and stores nothing.
-template <int N, int W, int J, int S>
+template <int N, int W, int J, int S, bool LL>
 __device__ __forceinline__ void estimate_tile(const uint32_t* __restrict__ slot_iq, int A, int CP, int U,
                                               const float2* __restrict__ pf, float2* __restrict__ Hs,
-                                              int a_wg, float2* lds, const FftTwiddles<N, S>& twr, int ps) {
+                                              int a_wg, float2* lds, const FftTwiddles<N, S, LL>& twr, int ps) {
   using Sh = FftShape<N>;
   constexpr int TPW = transforms_per_group<N, W>();
   const int li = threadIdx.x % Sh::L, ts = threadIdx.x / Sh::L;
@@ -170,10 +170,10 @@ __device__ __forceinline__ void estimate_tile(const uint32_t* __restrict__ slot_
 
 // Fill the last-pass twiddle table (once per workgroup) and load this lane's
 // twiddles.  Contains a workgroup barrier when the table is used.
-template <int N, int S>
-__device__ __forceinline__ void tile_setup(FftTwiddles<N, S>& twr, float2* twtab, const float2* __restrict__ tw) {
-  if constexpr (FftTwiddles<N, S>::kLdsLast) {
-    FftTwiddles<N, S>::P3Lds::fill(twtab, tw, threadIdx.x, blockDim.x);
+template <int N, int S, bool LL>
+__device__ __forceinline__ void tile_setup(FftTwiddles<N, S, LL>& twr, float2* twtab, const float2* __restrict__ tw) {
+  if constexpr (FftTwiddles<N, S, LL>::kLdsLast) {
+    FftTwiddles<N, S, LL>::P3Lds::fill(twtab, tw, threadIdx.x, blockDim.x);
     __syncthreads();
   }
   twr.load(tw, threadIdx.x % FftShape<N>::L, twtab);
@@ -260,8 +260,9 @@ struct SlotView {
 // Demodulate data symbol t of one slot with the W wavefronts of the
 // workgroup.  Uses the dynamic LDS `lds` (exchange buffers, then the
 // reduction rows); every thread of the workgroup must call it.
-template <int N, int QH, int W, bool ZF, int S>
-__device__ __forceinline__ void demod_tile(const SlotView& sv, int t, float2* lds, const FftTwiddles<N, S>& twr) {
+template <int N, int QH, int W, bool ZF, int S, bool LL>
+__device__ __forceinline__ void demod_tile(const SlotView& sv, int t, float2* lds,
+                                           const FftTwiddles<N, S, LL>& twr) {
   using Sh = FftShape<N>;
   constexpr int NI = 2 * QH;  // spectrum registers that can hold a used subcarrier
   static_assert(NI <= Sh::P, "window wider than the lane's spectrum");
@@ -498,16 +499,24 @@ __device__ __forceinline__ void demod_tile(const SlotView& sv, int t, float2* ld
 }
 
 
+// Where the uniform demod keeps the last pass's twiddles: in VGPRs (no LDS
+// reads in the antenna loop) where that leaves the kernel's wavefronts per
+// SIMD unchanged and was measured faster, N = 1024 (3 per SIMD at the widest
+// spectrum windows either way); elsewhere in the LDS table.
+template <int N, int QH>
+constexpr bool demod_twiddles_in_lds() { return !(N == 1024 && QH >= 5); }
+
 // Uniform slots: one workgroup per (slot, data symbol).
 template <int N, int QH, int W, bool ZF>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(RX_DEMOD_MIN_WAVES_PER_EU)))
 void demod_kernel(const uint32_t* __restrict__ iq, int64_t S, int A, int T, int CP, int U, int B,
                   const float2* __restrict__ tw, const float2* __restrict__ H, float2* __restrict__ xhat,
                   uint8_t* __restrict__ bits) {
+  using Tw = FftTwiddles<N, 0, demod_twiddles_in_lds<N, QH>()>;
   extern __shared__ float2 lds[];
-  __shared__ float2 twtab[FftTwiddles<N>::kLdsFloat2 > 0 ? FftTwiddles<N>::kLdsFloat2 : 1];
-  FftTwiddles<N> twr;
-  tile_setup<N>(twr, twtab, tw);
+  __shared__ float2 twtab[Tw::kLdsFloat2 > 0 ? Tw::kLdsFloat2 : 1];
+  Tw twr;
+  tile_setup(twr, twtab, tw);
   const int Td = T - 1;
   const int64_t item = xcd_remap(blockIdx.x, S * Td);
   const int64_t s = item / Td;

@@ -90,6 +90,8 @@ CASES = {
     "U_max": C2.replace(n_ant=4, fft_len=256, cp_len=18, n_used=254, bits_per_sym=4, n_slots=1, n_sym=3),
     "CP0_T2": C2.replace(n_ant=6, cp_len=0, n_sym=2, n_slots=2, n_taps=1),
     "U_not_mult_4": C2.replace(n_ant=3, n_used=598, n_slots=1, n_sym=3),
+    # 1000 of 1024 bins used: the widest spectrum window of the demod (8 + 8 registers per lane)
+    "N1024_U1000_wide": C2.replace(n_ant=6, n_used=1000, n_slots=2, n_sym=3),
 }
 
 

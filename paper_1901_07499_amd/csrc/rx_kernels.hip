@@ -180,15 +180,23 @@ __device__ __forceinline__ void tile_setup(FftTwiddles<N, S, LL>& twr, float2* t
 }
 
 // Uniform slots: workgroup = (slot, group of W*F*J antennas).
+// Last-pass twiddles of the estimate kernels: in VGPRs where the kernel runs
+// 2 wavefronts per SIMD either way (N >= 1024 in the workgroup grid below;
+// every batch kernel), in the LDS table where VGPRs would cost a wavefront
+// (N = 512, and the resident-grid kernel at 3 per SIMD).
+template <int N>
+constexpr bool estimate_twiddles_in_lds() { return N < 1024; }
+
 template <int N, int W, int J>
 __global__ __launch_bounds__(64 * W) void estimate_kernel(const uint32_t* __restrict__ iq, int A, int T, int CP,
                                                           int U, const float2* __restrict__ tw,
                                                           const float2* __restrict__ pf, float2* __restrict__ H,
                                                           int blocks_per_slot, int ps) {
+  using Tw = FftTwiddles<N, 0, estimate_twiddles_in_lds<N>()>;
   extern __shared__ float2 lds[];
-  __shared__ float2 twtab[FftTwiddles<N>::kLdsFloat2 > 0 ? FftTwiddles<N>::kLdsFloat2 : 1];
-  FftTwiddles<N> twr;
-  tile_setup<N>(twr, twtab, tw);
+  __shared__ float2 twtab[Tw::kLdsFloat2 > 0 ? Tw::kLdsFloat2 : 1];
+  Tw twr;
+  tile_setup(twr, twtab, tw);
   const int64_t s = blockIdx.x / blocks_per_slot;
   const int blk = blockIdx.x % blocks_per_slot;
   const int a_wg = blk * (transforms_per_group<N, W>() * J);
@@ -555,9 +563,10 @@ __global__ __launch_bounds__(64 * W) void batch_estimate_kernel(const FrameDesc*
                                                                 BatchIo io, const float2* __restrict__ tw,
                                                                 int* queue) {
   extern __shared__ float2 lds[];
-  __shared__ float2 twtab[FftTwiddles<N, S>::kLdsFloat2 > 0 ? FftTwiddles<N, S>::kLdsFloat2 : 1];
+  using Tw = FftTwiddles<N, S, false>;  // 2 wavefronts per SIMD either way
+  __shared__ float2 twtab[Tw::kLdsFloat2 > 0 ? Tw::kLdsFloat2 : 1];
   __shared__ int tile_sh, frame_sh;
-  FftTwiddles<N, S> twr;
+  Tw twr;
   tile_setup<N>(twr, twtab, tw);
   for (;;) {
     int frame;
@@ -576,9 +585,13 @@ __global__ __launch_bounds__(64 * W) void batch_demod_kernel(const FrameDesc* __
                                                              int* queue, int* done_count,
                                                              unsigned long long* done_time) {
   extern __shared__ float2 lds[];
-  __shared__ float2 twtab[FftTwiddles<N, S>::kLdsFloat2 > 0 ? FftTwiddles<N, S>::kLdsFloat2 : 1];
+  // the last-pass twiddle table in LDS keeps the schedule-0 kernels with the
+  // narrower window at 3 wavefronts per SIMD; the others run 2 either way and
+  // hold the twiddles in VGPRs
+  using Tw = FftTwiddles<N, S, (S == 0 && QH <= 5)>;
+  __shared__ float2 twtab[Tw::kLdsFloat2 > 0 ? Tw::kLdsFloat2 : 1];
   __shared__ int tile_sh, frame_sh;
-  FftTwiddles<N, S> twr;
+  Tw twr;
   tile_setup<N>(twr, twtab, tw);
   for (;;) {
     int frame;

@@ -224,7 +224,8 @@ int rx_batch_set_config(rx_batch_t batch, int32_t fft_len, int32_t demod_waves, 
                         int32_t dem_sched, int32_t est_sched);
 
 /* Radix schedule `sched` of the fft_len-point transform of the batch kernels
- * (paper Sec. II-B: the FFT stage): radices[0..2] receive the radix of each
+ * (paper Sec. II-B, the per-symbol FFT of the outline, and Sec. II-C, the
+ * batched FFT of all antennas' symbols): radices[0..2] receive the radix of each
  * Stockham pass, first pass first, 0 after the last pass (radix 16 first in
  * every schedule; 512, 1024 and 2048 have two schedules, 16-R-16 and 16-16-R,
  * the other lengths one).  RX_E_UNSUPPORTED when fft_len has no schedule

@@ -33,13 +33,9 @@
 #include "rx_fft.hpp"
 #include "rx_launch.h"
 
-// Tuning constants (compile time): wavefronts per demod workgroup and the
-// minimum wavefronts per SIMD the demod kernel's register budget must allow.
+// Tuning constants (compile time): wavefronts per demod workgroup.
 #ifndef RX_DEMOD_WAVES
 #define RX_DEMOD_WAVES 4
-#endif
-#ifndef RX_DEMOD_MIN_WAVES_PER_EU
-#define RX_DEMOD_MIN_WAVES_PER_EU 1
 #endif
 // Symbols a demod wavefront transforms side by side per loop iteration when
 // one transform fills the wavefront (N >= 1024): independent work that hides
@@ -508,15 +504,20 @@ __device__ __forceinline__ void demod_tile(const SlotView& sv, int t, float2* ld
 
 
 // Where the uniform demod keeps the last pass's twiddles: in VGPRs (no LDS
-// reads in the antenna loop) where that leaves the kernel's wavefronts per
-// SIMD unchanged and was measured faster, N = 1024 (3 per SIMD at the widest
-// spectrum windows either way); elsewhere in the LDS table.
+// reads in the antenna loop) for N = 1024 and 2048 at the widest spectrum
+// windows, where the kernel keeps its wavefronts per SIMD (3 at the 5-register
+// window, 2 at the 8-register one) and the 5-register kernels were measured
+// faster; elsewhere in the LDS table.  The N = 2048 kernel with the 5-register
+// window needs a register budget of 3 wavefronts per SIMD to stay there (168
+// VGPRs; without the bound the compiler takes 169 and drops to 2).
 template <int N, int QH>
-constexpr bool demod_twiddles_in_lds() { return !(N == 1024 && QH >= 5); }
+constexpr bool demod_twiddles_in_lds() { return !((N == 1024 || N == 2048) && QH >= 5); }
+template <int N, int QH>
+constexpr int demod_min_waves() { return N == 2048 && QH == 5 ? 3 : 1; }
 
 // Uniform slots: one workgroup per (slot, data symbol).
 template <int N, int QH, int W, bool ZF>
-__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(RX_DEMOD_MIN_WAVES_PER_EU)))
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(demod_min_waves<N, QH>())))
 void demod_kernel(const uint32_t* __restrict__ iq, int64_t S, int A, int T, int CP, int U, int B,
                   const float2* __restrict__ tw, const float2* __restrict__ H, float2* __restrict__ xhat,
                   uint8_t* __restrict__ bits) {

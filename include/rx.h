@@ -202,7 +202,8 @@ int rx_batch_process(rx_batch_t batch, const int16_t* iq, float* H, float* xhat,
  * class by class from the longest, within the whole batch graph with the
  * other classes as chosen so far: every shape with the class's schedules,
  * then every pair of schedules with the best shape, a choice replaced only
- * by one more than 1 % faster.  Synchronous; overwrites the outputs. */
+ * by one more than 1 % faster.  The whole batch runs 16 times first, untimed.
+ * Synchronous; overwrites the outputs. */
 int rx_batch_autotune(rx_batch_t batch, const int16_t* iq, float* H, float* xhat, uint8_t* bits,
                       void* workspace, int32_t reps, void* hip_stream);
 

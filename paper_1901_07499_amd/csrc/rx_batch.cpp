@@ -432,6 +432,13 @@ int rx_batch_autotune(rx_batch_t b, const int16_t* iq, float* H, float* xhat, ui
     (void)hipEventDestroy(e1);
     return RX_E_HIP;
   }
+  // Warm-up: a few launches of the whole batch graph, so the first
+  // configurations are not timed on an idle GPU whose clocks are still low.
+  if ((st = build_graph(b, io)) == RX_OK) {
+    for (int r = 0; r < 16 && st == RX_OK; r++)
+      if (hipGraphLaunch(b->exec, s) != hipSuccess) st = RX_E_HIP;
+    if (st == RX_OK && hipStreamSynchronize(s) != hipSuccess) st = RX_E_HIP;
+  }
   drop_graph(b);
   // Pass 1: each class alone, its estimate and demod kernels timed separately
   // (minimum over the timed runs: robust to interference); the estimate's

@@ -116,8 +116,10 @@ __global__ __launch_bounds__(kThreads) void sync_metric_kernel(const uint32_t* _
         const int c = ch.c[m + u];
 #pragma unroll
         for (int j = 0; j < 4; j++) {
-          re[j] += c * wr[(u + j) & 3];
-          im[j] += c * wi[(u + j) & 3];
+          // 24-bit products (samples are 16-bit, chips 8-bit): exact, and a
+          // full-rate multiply-add instead of a 32-bit integer multiply
+          re[j] += __mul24(c, wr[(u + j) & 3]);
+          im[j] += __mul24(c, wi[(u + j) & 3]);
         }
         unpack<4>(Y(m + u + 4), wr, wi, u);  // slot u now holds sample 4t + m + u + 4
       }
@@ -134,8 +136,8 @@ __global__ __launch_bounds__(kThreads) void sync_metric_kernel(const uint32_t* _
             vr = wr[k];
             vi = wi[k];
           }
-        re[j] += c * vr;
-        im[j] += c * vi;
+        re[j] += __mul24(c, vr);
+        im[j] += __mul24(c, vi);
       }
       const int s = m & 3;
       const uint32_t nx = Y(m + 4);

@@ -109,19 +109,40 @@ __global__ __launch_bounds__(kThreads) void sync_metric_kernel(const uint32_t* _
     for (int j = 0; j < 4; j++) unpack<4>(Y(j), wr, wi, j);
     int re[4] = {0, 0, 0, 0}, im[4] = {0, 0, 0, 0};
     // window slot (m + j) % 4 holds sample 4t + m + j
+    // Steps of four chips, software-pipelined: the next step's chips (one
+    // dword, little-endian bytes) and window samples are requested once this
+    // step has taken its own, so the wait for them (one counter for scalar and
+    // LDS loads) falls a whole step after they were issued.
     int m = 0;
-    for (; m + 4 <= L; m += 4) {
+    if (L >= 4) {
+      int cn;
+      uint32_t yn[4];
+      __builtin_memcpy(&cn, ch.c, 4);
 #pragma unroll
-      for (int u = 0; u < 4; u++) {
-        const int c = ch.c[m + u];
+      for (int u = 0; u < 4; u++) yn[u] = Y(u + 4);
+      for (; m + 4 <= L; m += 4) {
+        const int cw = cn;
+        uint32_t yc[4];
 #pragma unroll
-        for (int j = 0; j < 4; j++) {
-          // 24-bit products (samples are 16-bit, chips 8-bit): exact, and a
-          // full-rate multiply-add instead of a 32-bit integer multiply
-          re[j] += __mul24(c, wr[(u + j) & 3]);
-          im[j] += __mul24(c, wi[(u + j) & 3]);
+        for (int u = 0; u < 4; u++) yc[u] = yn[u];
+        __builtin_amdgcn_sched_barrier(0);
+        if (m + 8 <= L) {
+          __builtin_memcpy(&cn, ch.c + m + 4, 4);
+#pragma unroll
+          for (int u = 0; u < 4; u++) yn[u] = Y(m + u + 8);
         }
-        unpack<4>(Y(m + u + 4), wr, wi, u);  // slot u now holds sample 4t + m + u + 4
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+          const int c = (int)(int8_t)(uint32_t)(cw >> (8 * u));  // chip m + u
+#pragma unroll
+          for (int j = 0; j < 4; j++) {
+            // 24-bit products (samples are 16-bit, chips 8-bit): exact, and a
+            // full-rate multiply-add instead of a 32-bit integer multiply
+            re[j] += __mul24(c, wr[(u + j) & 3]);
+            im[j] += __mul24(c, wi[(u + j) & 3]);
+          }
+          unpack<4>(yc[u], wr, wi, u);  // slot u now holds sample 4t + m + u + 4
+        }
       }
     }
     for (; m < L; m++) {  // tail: rotate by hand

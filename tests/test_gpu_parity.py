@@ -92,6 +92,8 @@ CASES = {
     "U_not_mult_4": C2.replace(n_ant=3, n_used=598, n_slots=1, n_sym=3),
     # 1000 of 1024 bins used: the widest spectrum window of the demod (8 + 8 registers per lane)
     "N1024_U1000_wide": C2.replace(n_ant=6, n_used=1000, n_slots=2, n_sym=3),
+    # 1600 of 2048 bins: the 2048-point demod's 8 + 8 register window
+    "N2048_U1600_wide": C4.replace(n_ant=3, n_used=1600, n_slots=2, n_sym=3),
 }
 
 

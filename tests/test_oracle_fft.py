@@ -82,3 +82,21 @@ def test_fft_parseval_roundtrip_linearity(n):
 def test_fft_rejects_non_power_of_two():
     with pytest.raises(ValueError):
         oracle.fft(np.ones(12, complex))
+
+
+@pytest.mark.parametrize("S,T,A,N,CP", [(2, 3, 3, 64, 16), (3, 4, 5, 128, 9), (2, 3, 4, 64, 0)])
+def test_fft_symbols_is_cp_strip_then_numpy_fft(S, T, A, N, CP):
+    """CP removal + FFT of every antenna's symbol (paper Sec. II-B): each
+    [S][T][A] record of the int16 buffer loses its first CP samples and the
+    remaining N go through the forward DFT, output in [s][t][a][k] order.
+    Every record holds different random samples (CP included), so a wrong slot
+    stride, symbol/antenna order or CP offset shows as a mismatch."""
+    rng = np.random.default_rng(1000 * S + 100 * T + 10 * A + CP)
+    iq = rng.integers(-32768, 32768, size=(S, T, A, CP + N, 2), dtype=np.int16)
+    pilot = np.ones(N // 2, dtype=np.complex128)
+    got = oracle.fft_symbols(iq, pilot, n_ant=A, fft_len=N, cp_len=CP, n_used=N // 2, n_sym=T, bits_per_sym=2)
+    assert got.shape == (S, T, A, N)
+    y = iq[..., CP:, 0].astype(np.float64) + 1j * iq[..., CP:, 1].astype(np.float64)
+    ref = np.fft.fft(y, axis=-1)
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(got - ref)) <= 1e-12 * scale

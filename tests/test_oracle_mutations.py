@@ -37,6 +37,10 @@ MUTANTS = {
     "demap_16qam_threshold": ("sqrt(10.0) > 2.0", "sqrt(10.0) > 3.0"),
     "demap_64qam_third_bit": ("fabs(u - 4.0) > 2.0", "fabs(u - 4.0) < 2.0"),
     "demap_axes_swapped": ("bitvals[i * bits_per_sym + 2 * j] = re[j];", "bitvals[i * bits_per_sym + 2 * j] = im[j];"),
+    "fft_symbols_slot_stride": ("size_t slot_elems = (size_t)T * A * (N + p->cp_len) * 2;",
+                                "size_t slot_elems = (size_t)T * A * N * 2;"),
+    "fft_symbols_output_order": ("double* o = out + ((((size_t)s * T + t) * A + a) * N) * 2;",
+                                 "double* o = out + ((((size_t)s * A + a) * T + t) * N) * 2;"),
     "pack_lsb_first": ("v = (uint8_t)((v << 1) | (bitvals[8 * i + j] & 1));",
                        "v = (uint8_t)(v | ((bitvals[8 * i + j] & 1) << j));"),
 }

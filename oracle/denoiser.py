@@ -106,6 +106,21 @@ def forward(theta: np.ndarray, h: np.ndarray, *, bf16_ops: bool = False, cache: 
     return out
 
 
+def ls_fallback(h: np.ndarray, out: np.ndarray, max_corr: float = 1.0):
+    """Plain LS as the refinement's fallback and judge: row r keeps its LS
+    estimate h[r] when the correction c = out[r] - h[r] has a non-finite entry
+    or carries more energy than max_corr^2 times the row's own,
+    sum_d |c[d]|^2 > max_corr^2 sum_d |h[d]|^2.  (An ideal denoiser removes
+    noise, and the noise's energy never exceeds the noisy estimate's.)
+    Returns (the rows kept or refined, boolean mask of rows that fell back)."""
+    h = np.asarray(h, dtype=np.complex128)
+    out = np.asarray(out, dtype=np.complex128)
+    with np.errstate(invalid="ignore", over="ignore"):
+        e = np.sum(np.abs(out - h) ** 2, axis=-1)
+        fell = ~np.isfinite(e) | ~(e <= max_corr ** 2 * np.sum(np.abs(h) ** 2, axis=-1))
+    return np.where(fell[:, None], h, out), fell
+
+
 def loss_grad(theta: np.ndarray, h: np.ndarray, h_true: np.ndarray, *, bf16_ops: bool = False):
     """Training loss and its gradient with respect to theta (analytic backward)."""
     h = np.asarray(h, dtype=np.complex128)

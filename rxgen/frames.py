@@ -281,12 +281,21 @@ def make_frames(cfg: FrameConfig, n_slots: Optional[int] = None, seed: Optional[
             for s in range(S)]
     if workers > 1 and S > 1:
         import multiprocessing as mp
-        with mp.get_context("fork").Pool(min(workers, S)) as pool:
-            results = pool.imap(_slot_job, jobs, chunksize=1)
-            for s, r in enumerate(results):
+        # close() + join() rather than the context manager, whose exit
+        # terminates the workers with SIGTERM (a profiler's signal handler in
+        # them reports that as an abort)
+        pool = mp.get_context("fork").Pool(min(workers, S))
+        try:
+            for s, r in enumerate(pool.imap(_slot_job, jobs, chunksize=1)):
                 iq[s], bits[s], X[s], H[s], snr[s], scl[s], y = r
                 if keep_float:
                     yk[s] = y
+            pool.close()
+        except BaseException:
+            pool.terminate()
+            raise
+        finally:
+            pool.join()
     else:
         for s, job in enumerate(jobs):
             iq[s], bits[s], X[s], H[s], snr[s], scl[s], y = _slot_job(job)
@@ -335,8 +344,15 @@ def make_batch(n_frames: int, seed: int, workers: int = 1, **shape_choices) -> B
     cfgs = [batch_frame_config(seed, i, **shape_choices) for i in range(n_frames)]
     if workers > 1 and n_frames > 1:
         import multiprocessing as mp
-        with mp.get_context("fork").Pool(min(workers, n_frames)) as pool:
+        pool = mp.get_context("fork").Pool(min(workers, n_frames))
+        try:
             frames = list(pool.imap(_batch_job, cfgs, chunksize=1))
+            pool.close()
+        except BaseException:
+            pool.terminate()
+            raise
+        finally:
+            pool.join()
     else:
         frames = [_batch_job(c) for c in cfgs]
     iq = np.concatenate([f.iq.reshape(-1) for f in frames])

@@ -177,3 +177,44 @@ def test_training_reduces_loss(seed):
         first = loss if first is None else first
         th, m, v = dn.adam(th, m, v, g, t, 3e-3)
     assert dn.loss_grad(th, h, h_true)[0] < 0.8 * first
+
+
+def _bias_only(b0, b1=0.0):
+    th = init_denoiser_params(3).astype(np.float64)
+    layers = dn.unpack(th)
+    layers[3][0][...] = 0.0
+    layers[3][1][...] = (b0, b1)
+    return dn.pack(layers)
+
+
+def test_ls_fallback_threshold_closed_form():
+    # a last layer of bias (b, 0) alone corrects every subcarrier by s*b, so the
+    # correction's energy is b^2 times the row's: kept below max_corr, LS above
+    h = _rows(3, 50, 12)
+    for b, mc, want in ((0.9, 1.0, False), (1.1, 1.0, True), (1.5, 2.0, False), (1.5, 1.4, True),
+                        (-0.99, 1.0, False)):
+        out = dn.forward(_bias_only(b), h)
+        got, fell = dn.ls_fallback(h, out, max_corr=mc)
+        assert np.all(fell == want), (b, mc)
+        np.testing.assert_array_equal(got, h if want else out)
+
+
+def test_ls_fallback_per_row_and_non_finite():
+    h = _rows(4, 20, 13)
+    out = h + 0.5 * h                       # correction energy 0.25 of the row's: kept
+    out[1] = h[1] + 2.0 * h[1]              # 4x: LS
+    out[2, 7] = np.nan                      # non-finite refinement: LS
+    got, fell = dn.ls_fallback(h, out)
+    np.testing.assert_array_equal(fell, [False, True, True, False])
+    np.testing.assert_array_equal(got[[1, 2]], h[[1, 2]])
+    np.testing.assert_array_equal(got[[0, 3]], out[[0, 3]])
+    # with no energy limit an infinite output still falls back
+    out2 = h.copy()
+    out2[3, 0] = np.inf
+    _, fell2 = dn.ls_fallback(h, out2, max_corr=np.inf)
+    np.testing.assert_array_equal(fell2, [False, False, False, True])
+    # a zero row that passes through keeps its (zero) estimate, not a fallback
+    hz = h.copy()
+    hz[0] = 0
+    _, fell3 = dn.ls_fallback(hz, dn.forward(_bias_only(0.5), hz))
+    assert not fell3[0]

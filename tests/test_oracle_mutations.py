@@ -112,6 +112,9 @@ DN_MUTANTS = {
     "scale_is_mean_abs": ("np.sqrt(np.mean(np.abs(h) ** 2, axis=-1))", "np.mean(np.abs(h), axis=-1)"),
     "adam_no_bias_correction": ("mh = m / (1 - beta1 ** step)", "mh = m"),
     "adam_sqrt_missing": ("(np.sqrt(vh) + eps)", "(vh + eps)"),
+    "fallback_inverted": ("fell = ~np.isfinite(e) | ~(e <= max_corr", "fell = ~np.isfinite(e) | (e <= max_corr"),
+    "fallback_limit_not_squared": ("~(e <= max_corr ** 2 * np.sum", "~(e <= max_corr * np.sum"),
+    "fallback_ignores_non_finite": ("fell = ~np.isfinite(e) | ~(e", "fell = ~(e"),
     "bf16_truncates": ("(u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000", "u & 0xFFFF0000"),
 }
 

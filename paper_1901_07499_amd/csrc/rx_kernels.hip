@@ -370,9 +370,11 @@ __device__ __forceinline__ void demod_tile(const SlotView& sv, int t, float2* ld
         // the antenna is uniform over the wavefront: row offset in a scalar
         // register, per-lane offsets loop-invariant, no address arithmetic; a
         // transform past A reads through an empty resource, which returns 0
+        // (with one symbol per wavefront job, C == 1, the loop bound already
+        // keeps au below A)
         const int au = __builtin_amdgcn_readfirstlane(a);
         const int so = (au < A ? au : A - 1) * (U * 8);
-        const __amdgpu_buffer_rsrc_t rs = (Sh::WPT == 1 || au < A) ? hrs : hrs_empty;
+        const __amdgpu_buffer_rsrc_t rs = ((Sh::WPT == 1 && C == 1) || au < A) ? hrs : hrs_empty;
 #pragma unroll
         for (int i = 0; i < NI; i++)
           hv[i] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, hoff[i], so, 0));

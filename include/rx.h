@@ -272,9 +272,25 @@ int rx_dn_destroy(rx_dn_t dn);
 /* Load parameters (device float [RX_DN_PARAMS]) into the denoiser. */
 int rx_dn_load(rx_dn_t dn, const float* params, void* hip_stream);
 
-/* out = refined rows.  H_out may equal H_in (each row is read before it is
- * written); otherwise the two must not overlap.  rows == 0 is a no-op. */
+/* out = refined rows, with plain LS as the fallback: a row keeps its input
+ * (LS) estimate when its correction c = out - h has a non-finite entry or
+ * carries more energy than the row, sum_d |c[d]|^2 > max_corr^2 sum_d |h[d]|^2
+ * (max_corr from rx_dn_set_fallback, default 1: a refinement that removes
+ * noise never changes a row by more than the row itself).  Without loaded
+ * parameters every row keeps its LS estimate.  H_out may equal H_in (each row
+ * is read before it is written); otherwise the two must not overlap.
+ * rows == 0 is a no-op. */
 int rx_dn_apply(rx_dn_t dn, const float* H_in, int64_t rows, float* H_out, void* hip_stream);
+
+/* rx_dn_apply that also reports, per row, whether it kept LS: fell device
+ * uint8 [rows] (1 = LS kept, 0 = refined) or NULL; it must not overlap the
+ * row buffers. */
+int rx_dn_apply_judged(rx_dn_t dn, const float* H_in, int64_t rows, float* H_out, uint8_t* fell,
+                       void* hip_stream);
+
+/* Threshold of the LS fallback: max_corr > 0, +infinity keeps only rows whose
+ * correction is not finite.  Host only; applies to later calls. */
+int rx_dn_set_fallback(rx_dn_t dn, float max_corr);
 
 /* Device scratch for rx_dn_grad and rx_dn_train_step on `rows` rows
  * (activations and deltas in bf16, per-workgroup partial sums). */

@@ -121,8 +121,17 @@ def ls_fallback(h: np.ndarray, out: np.ndarray, max_corr: float = 1.0):
     return np.where(fell[:, None], h, out), fell
 
 
-def loss_grad(theta: np.ndarray, h: np.ndarray, h_true: np.ndarray, *, bf16_ops: bool = False):
-    """Training loss and its gradient with respect to theta (analytic backward)."""
+def loss_grad(theta: np.ndarray, h: np.ndarray, h_true: np.ndarray, *, bf16_ops: bool = False,
+              term_rss: bool = False):
+    """Training loss and its gradient with respect to theta (analytic backward).
+
+    Each gradient entry is a sum over rows and positions of products
+    delta * x (weights) or of deltas (biases).  With ``term_rss`` a third
+    result gives, per entry, the root of the sum of those terms' squares: the
+    scale of the difference a second implementation makes when it rounds a
+    few of the terms' operands to the other neighbouring bf16 value
+    (independent errors of relative size u on the terms add up to about
+    u * rss)."""
     h = np.asarray(h, dtype=np.complex128)
     h_true = np.asarray(h_true, dtype=np.complex128)
     rnd = bf16 if bf16_ops else (lambda v: v)
@@ -142,6 +151,7 @@ def loss_grad(theta: np.ndarray, h: np.ndarray, h_true: np.ndarray, *, bf16_ops:
     delta = rnd(2.0 * e / n)  # dL/da4
     layers = unpack(theta)
     grads = [None] * len(layers)
+    rss = [None] * len(layers)
     for li in range(len(layers) - 1, -1, -1):
         W, _ = layers[li]
         Wr = rnd(W)
@@ -153,6 +163,11 @@ def loss_grad(theta: np.ndarray, h: np.ndarray, h_true: np.ndarray, *, bf16_ops:
             gW[:, :, k] = np.einsum("rou,rcu->oc", delta, xp[:, :, k:k + U])
         gb = delta.sum(axis=(0, 2))
         grads[li] = (gW, gb)
+        if term_rss:
+            qW = np.empty_like(W)
+            for k in range(TAPS):
+                qW[:, :, k] = np.einsum("rou,rcu->oc", delta ** 2, xp[:, :, k:k + U] ** 2)
+            rss[li] = (np.sqrt(qW), np.sqrt((delta ** 2).sum(axis=(0, 2))))
         if li == 0:
             break
         # dL/dx_{li} = transposed correlation of delta with W, then the ReLU mask
@@ -163,6 +178,8 @@ def loss_grad(theta: np.ndarray, h: np.ndarray, h_true: np.ndarray, *, bf16_ops:
             # x[d + k - 3] fed a[d]: so dx[u] += W[:, :, k]^T delta[u - k + 3]
             gx += np.einsum("oc,rou->rcu", Wr[:, :, k], dp[:, :, 2 * HALF - k:2 * HALF - k + U])
         delta = rnd(gx * (xin > 0))
+    if term_rss:
+        return loss, pack(grads), pack(rss)
     return loss, pack(grads)
 
 

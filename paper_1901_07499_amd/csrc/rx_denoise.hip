@@ -6,6 +6,8 @@
 //   a_l = b_l + sum_{ci,k} W_l[co][ci][k] x_{l-1}[ci][d+k-3]    (7 taps, zero outside 0..U-1)
 //   x_l = max(a_l, 0) (l = 1, 2, 3);  channels 2 -> 32 -> 32 -> 32 -> 2
 //   out = h + s (a_4[0] + i a_4[1])
+// LS stays the fallback: at inference a row keeps h when the correction
+// out - h has non-finite energy or more than max_corr^2 times sum |h|^2.
 // Training loss: mean over rows and d of |x0 + a_4 - h_true / s|^2.
 // The paper computes the LS estimate only (Sec. II-C, LS paragraph); this
 // refinement and its comb-pilot input extend it.
@@ -303,8 +305,10 @@ __global__ __launch_bounds__(kBlock) void dn_forward_kernel(const float2* __rest
       hrow[d] = v;
       ss = fmaf(v.x, v.x, fmaf(v.y, v.y, ss));
     }
-    const float s = sqrtf(block_sum(ss, red) / (float)U);
+    const float hs = block_sum(ss, red);  // sum_d |h[d]|^2
+    const float s = sqrtf(hs / (float)U);
     const float inv = s > 0.f ? 1.0f / s : 0.f;  // a zero row passes through (out = h)
+    float ce = 0.f;                               // inference: energy of the correction s * a_4
 
     for (int t0 = 0; t0 < U; t0 += TO) {
       __syncthreads();  // the previous tile's readers are done
@@ -391,6 +395,8 @@ __global__ __launch_bounds__(kBlock) void dn_forward_kernel(const float2* __rest
         const float2 h = hrow[p];
         if (!TRAIN) {
           Hout[row * U + p] = make_float2(fmaf(s, o0, h.x), fmaf(s, o1, h.y));
+          const float cx = s * o0, cy = s * o1;
+          ce = fmaf(cx, cx, fmaf(cy, cy, ce));
         } else {
           const float2 t = io.Htrue[row * U + p];
           const float ex = h.x * inv + o0 - t.x * inv;
@@ -402,6 +408,23 @@ __global__ __launch_bounds__(kBlock) void dn_forward_kernel(const float2* __rest
           io.D4[(row * 2 + 1) * UP + p] = (bfbits)bf16_bits(c * ey);
         }
       }
+    }
+    if (!TRAIN) {
+      // LS fallback: the row keeps its LS estimate when the correction's
+      // energy is not finite or exceeds max_corr^2 times the row's own (NaN
+      // compares false, so it falls back too).  The rewrite uses the thread
+      // that wrote each position above, so it lands after that store.
+      const float E = block_sum(ce, red);
+      const bool fell = !__builtin_isfinite(E) || !(E <= io.fb_max2 * hs);
+      if (fell) {
+        for (int t0 = 0; t0 < U; t0 += TO)
+          for (int i = tid; i < TO; i += kBlock) {
+            const int p = t0 + i;
+            if (p >= U) break;
+            Hout[row * U + p] = hrow[p];
+          }
+      }
+      if (tid == 0 && io.fell) io.fell[row] = fell ? 1 : 0;
     }
   }
   if (TRAIN) {
@@ -850,6 +873,20 @@ size_t bwd_lds() { return (size_t)2 * dn::NPOS * dn::RS * 2 + dn::NPOS * 4; }
 
 int dn_grid(int64_t rows) { return (int)(rows < kMaxGrid ? rows : kMaxGrid); }
 
+namespace {
+__global__ void fill_u8_kernel(uint8_t* __restrict__ p, uint8_t v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+}  // namespace
+
+hipError_t fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(fill_u8_kernel, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256), 0, st, p, v, n);
+  return hipGetLastError();
+}
+
 hipError_t dn_relayout(const float* theta, uint16_t* frag, hipStream_t st) {
   const int n = kFragUnits * 8;
   hipLaunchKernelGGL(dn::dn_relayout_kernel, dim3((n + dn::kBlock - 1) / dn::kBlock), dim3(dn::kBlock), 0, st,
@@ -858,8 +895,10 @@ hipError_t dn_relayout(const float* theta, uint16_t* frag, hipStream_t st) {
 }
 
 hipError_t dn_apply(const float2* Hin, int64_t rows, int U, const void* frag, const float* theta, float2* Hout,
-                    hipStream_t st) {
+                    float fb_max2, uint8_t* fell, hipStream_t st) {
   DnTrainIo io{};
+  io.fb_max2 = fb_max2;
+  io.fell = fell;
   hipLaunchKernelGGL(dn::dn_forward_kernel<false>, dim3(dn_grid(rows)), dim3(dn::kBlock), fwd_lds(U), st, Hin,
                      rows, U, reinterpret_cast<const dn::bf16x8*>(frag), theta, Hout, io);
   return hipGetLastError();

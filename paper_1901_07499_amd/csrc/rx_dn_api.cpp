@@ -16,6 +16,7 @@ struct rx_dn_s {
   int U = 0;
   int device = -1;
   bool loaded = false;
+  float max_corr = 1.0f;     // LS fallback threshold (rx_dn_set_fallback)
   float* theta = nullptr;    // [kParams], the loaded parameters (biases are read from here)
   uint16_t* frag = nullptr;  // [kFragUnits * 8] bf16 operand layout
 };
@@ -108,18 +109,42 @@ int rx_dn_load(rx_dn_t dn, const float* params, void* hip_stream) {
   return RX_OK;
 }
 
-int rx_dn_apply(rx_dn_t dn, const float* H_in, int64_t rows, float* H_out, void* hip_stream) {
+int rx_dn_set_fallback(rx_dn_t dn, float max_corr) {
+  if (!dn || !(max_corr > 0.f)) return RX_E_INVALID_ARG;  // NaN fails the test too
+  dn->max_corr = max_corr;
+  return RX_OK;
+}
+
+int rx_dn_apply_judged(rx_dn_t dn, const float* H_in, int64_t rows, float* H_out, uint8_t* fell,
+                       void* hip_stream) {
   int st = check_dn(dn);
   if (st != RX_OK) return st;
   if ((st = check_rows(dn, rows)) != RX_OK) return st;
   if (rows == 0) return RX_OK;
-  if (!dn->loaded || !H_in || !H_out || !aligned(H_in, 8) || !aligned(H_out, 8)) return RX_E_INVALID_ARG;
+  if (!H_in || !H_out || !aligned(H_in, 8) || !aligned(H_out, 8)) return RX_E_INVALID_ARG;
   const size_t bytes = (size_t)rows * dn->U * 8;
   const uintptr_t a = (uintptr_t)H_in, b = (uintptr_t)H_out;
   if (a != b && a < b + bytes && b < a + bytes) return RX_E_INVALID_ARG;  // partial overlap
+  if (fell) {
+    const uintptr_t f = (uintptr_t)fell;
+    if ((f < a + bytes && a < f + (size_t)rows) || (f < b + bytes && b < f + (size_t)rows))
+      return RX_E_INVALID_ARG;  // flags overlap a row buffer
+  }
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (!dn->loaded) {
+    // no refinement loaded: every row keeps its LS estimate
+    if (a != b && hipMemcpyAsync(H_out, H_in, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess) return RX_E_HIP;
+    if (fell && rx::fill_u8(fell, 1, rows, s) != hipSuccess) return RX_E_HIP;
+    return RX_OK;
+  }
+  const float mc2 = dn->max_corr * dn->max_corr;
   const hipError_t e = rx::dn_apply(reinterpret_cast<const float2*>(H_in), rows, dn->U, dn->frag, dn->theta,
-                                    reinterpret_cast<float2*>(H_out), static_cast<hipStream_t>(hip_stream));
+                                    reinterpret_cast<float2*>(H_out), mc2, fell, s);
   return e == hipSuccess ? RX_OK : RX_E_HIP;
+}
+
+int rx_dn_apply(rx_dn_t dn, const float* H_in, int64_t rows, float* H_out, void* hip_stream) {
+  return rx_dn_apply_judged(dn, H_in, rows, H_out, nullptr, hip_stream);
 }
 
 size_t rx_dn_workspace_bytes(rx_dn_t dn, int64_t rows) {

@@ -93,6 +93,9 @@ struct DnTrainIo {
   uint32_t *M1, *M2, *M3;       // ReLU masks of x1..x3: [row][UP], bit c = (x[c] > 0)
   float* part;       // [grid][kParams] weight-gradient partials
   float* loss_part;  // [grid]
+  // inference only: LS fallback threshold (max_corr^2) and per-row flags (or null)
+  float fb_max2;
+  uint8_t* fell;
 };
 
 struct AdamArgs {
@@ -110,8 +113,10 @@ struct GenArgs {
 
 int dn_grid(int64_t rows);
 hipError_t dn_relayout(const float* theta, uint16_t* frag, hipStream_t st);
+// p[0 .. n) = v (a kernel rather than hipMemsetAsync, so callers may capture it).
+hipError_t fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t st);
 hipError_t dn_apply(const float2* Hin, int64_t rows, int U, const void* frag, const float* theta, float2* Hout,
-                    hipStream_t st);
+                    float fb_max2, uint8_t* fell, hipStream_t st);
 hipError_t dn_train(const float2* Hin, const float2* Htrue, int64_t rows, int U, const void* frag,
                     const float* theta, const DnTrainIo& io, float* grad, float* loss, const AdamArgs& adam,
                     hipStream_t st);

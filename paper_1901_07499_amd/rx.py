@@ -28,7 +28,8 @@ EXPORTS = ("rx_params_check", "rx_plan_create", "rx_plan_destroy", "rx_workspace
            "rx_batch_create", "rx_batch_destroy", "rx_batch_layout", "rx_batch_workspace_bytes",
            "rx_batch_process", "rx_batch_autotune", "rx_batch_config", "rx_batch_schedules", "rx_batch_set_config",
            "rx_fft_radices", "rx_batch_frame_latency",
-           "rx_dn_create", "rx_dn_destroy", "rx_dn_load", "rx_dn_apply", "rx_dn_workspace_bytes", "rx_dn_grad",
+           "rx_dn_create", "rx_dn_destroy", "rx_dn_load", "rx_dn_apply", "rx_dn_apply_judged", "rx_dn_set_fallback",
+           "rx_dn_workspace_bytes", "rx_dn_grad",
            "rx_dn_train_step", "rx_dn_generate", "rx_sync_workspace_bytes", "rx_sync_find", "rx_sync_extract")
 RX_DN_PARAMS = 15330
 
@@ -97,6 +98,8 @@ def _load() -> ctypes.CDLL:
     lib.rx_dn_destroy.argtypes = [vp]
     lib.rx_dn_load.argtypes = [vp, vp, vp]
     lib.rx_dn_apply.argtypes = [vp, vp, i64, vp, vp]
+    lib.rx_dn_apply_judged.argtypes = [vp, vp, i64, vp, vp, vp]
+    lib.rx_dn_set_fallback.argtypes = [vp, f32]
     lib.rx_dn_workspace_bytes.argtypes = [vp, i64]
     lib.rx_dn_workspace_bytes.restype = sz
     lib.rx_dn_grad.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp]
@@ -227,6 +230,14 @@ def rx_dn_load(dn, params, stream) -> int:
 
 def rx_dn_apply(dn, H_in, rows, H_out, stream) -> int:
     return _lib.rx_dn_apply(dn, H_in, rows, H_out, stream)
+
+
+def rx_dn_apply_judged(dn, H_in, rows, H_out, fell, stream) -> int:
+    return _lib.rx_dn_apply_judged(dn, H_in, rows, H_out, fell, stream)
+
+
+def rx_dn_set_fallback(dn, max_corr) -> int:
+    return _lib.rx_dn_set_fallback(dn, max_corr)
 
 
 def rx_dn_workspace_bytes(dn, rows) -> int:
@@ -543,15 +554,24 @@ class Denoiser:
         if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
             raise ValueError(f"expected a contiguous float32 CUDA tensor of shape {shape}")
 
-    def apply(self, H, out=None):
+    def apply(self, H, out=None, flags: bool = False):
+        """Refined rows (LS kept where the refinement is not trusted); with
+        ``flags`` also a uint8 tensor [rows], 1 where a row kept LS."""
         import torch
         rows = H.shape[0]
         self._check(H, (rows, self.n_used, 2))
         out = torch.empty_like(H) if out is None else out
-        st = rx_dn_apply(self._dn, H.data_ptr(), rows, out.data_ptr(), self._stream())
+        fell = torch.empty((max(rows, 1),), dtype=torch.uint8, device=H.device) if flags else None
+        st = rx_dn_apply_judged(self._dn, H.data_ptr(), rows, out.data_ptr(),
+                                None if fell is None else fell.data_ptr(), self._stream())
         if st != RX_OK:
-            raise RxError(st, "rx_dn_apply")
-        return out
+            raise RxError(st, "rx_dn_apply_judged")
+        return (out, fell[:rows]) if flags else out
+
+    def set_fallback(self, max_corr: float):
+        st = rx_dn_set_fallback(self._dn, max_corr)
+        if st != RX_OK:
+            raise RxError(st, "rx_dn_set_fallback")
 
     def workspace(self, rows: int):
         import torch

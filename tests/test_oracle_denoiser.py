@@ -116,6 +116,51 @@ def test_gradient_matches_central_differences():
     np.testing.assert_allclose(g[idx], fd, rtol=1e-5, atol=1e-7 * scale)
 
 
+def test_gradient_term_rss_from_single_row_gradients():
+    # One position per row (U = 1): every gradient entry is a sum over rows of
+    # one term each, and row r's term is the gradient of row r alone divided
+    # by the row count (the loss is a mean; 8 rows keep the scaling exact).
+    rng = np.random.default_rng(41)
+    th = init_denoiser_params(41, last_scale=1.0).astype(np.float64) + 0.05 * rng.standard_normal(15330)
+    R = 8
+    h = rng.standard_normal((R, 1)) + 1j * rng.standard_normal((R, 1))
+    ht = h + 0.3 * (rng.standard_normal((R, 1)) + 1j * rng.standard_normal((R, 1)))
+    _, g, rss = dn.loss_grad(th, h, ht, term_rss=True)
+    singles = np.stack([dn.loss_grad(th, h[r:r + 1], ht[r:r + 1])[1] / R for r in range(R)])
+    np.testing.assert_allclose(g, singles.sum(axis=0), rtol=1e-10, atol=1e-14)
+    np.testing.assert_allclose(rss, np.sqrt((singles ** 2).sum(axis=0)), rtol=1e-10, atol=1e-14)
+
+
+def test_gradient_term_rss_last_layer_brute_force():
+    # Last layer, several positions: the terms are delta4[co][p] x3[ci][p+k-3]
+    # with delta4 = 2 (x0 + a4 - h_true / s) / (R U), summed by explicit loops.
+    rng = np.random.default_rng(43)
+    th = init_denoiser_params(43, last_scale=1.0).astype(np.float64) + 0.05 * rng.standard_normal(15330)
+    R, U = 2, 5
+    h = _rows(R, U, 44, smooth=False)
+    ht = h + 0.3 * _rows(R, U, 45, smooth=False)
+    _, _, rss = dn.loss_grad(th, h, ht, term_rss=True)
+    _, acts, s = dn.forward(th, h, cache=True)
+    x3, a4 = acts[3], acts[4]
+    d4 = np.empty((R, 2, U))
+    for r in range(R):
+        t = ht[r] / s[r]
+        x0 = h[r] / s[r]
+        d4[r, 0] = 2 * (x0.real + a4[r, 0] - t.real) / (R * U)
+        d4[r, 1] = 2 * (x0.imag + a4[r, 1] - t.imag) / (R * U)
+    want_w = np.zeros((2, 32, 7))
+    for co in range(2):
+        for ci in range(32):
+            for k in range(7):
+                for r in range(R):
+                    for p in range(U):
+                        if 0 <= p + k - 3 < U:
+                            want_w[co, ci, k] += (d4[r, co, p] * x3[r, ci, p + k - 3]) ** 2
+    got_w = rss[15330 - 2 - 2 * 32 * 7:15330 - 2].reshape(2, 32, 7)
+    np.testing.assert_allclose(got_w, np.sqrt(want_w), rtol=1e-10, atol=1e-15)
+    np.testing.assert_allclose(rss[-2:], np.sqrt((d4 ** 2).sum(axis=(0, 2))), rtol=1e-12)
+
+
 def test_bf16_rounding_matches_torch():
     rng = np.random.default_rng(3)
     x = np.concatenate([rng.standard_normal(4000) * 10.0 ** rng.integers(-8, 8, 4000),

@@ -116,6 +116,10 @@ DN_MUTANTS = {
     "fallback_limit_not_squared": ("~(e <= max_corr ** 2 * np.sum", "~(e <= max_corr * np.sum"),
     "fallback_ignores_non_finite": ("fell = ~np.isfinite(e) | ~(e", "fell = ~(e"),
     "bf16_truncates": ("(u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000", "u & 0xFFFF0000"),
+    "term_rss_not_squared": ("np.einsum(\"rou,rcu->oc\", delta ** 2, xp[:, :, k:k + U] ** 2)",
+                             "np.einsum(\"rou,rcu->oc\", delta ** 2, xp[:, :, k:k + U])"),
+    "term_rss_tap_shifted": ("delta ** 2, xp[:, :, k:k + U] ** 2", "delta ** 2, xp[:, :, 2 * HALF - k:2 * HALF - k + U] ** 2"),
+    "term_rss_bias_unsquared": ("np.sqrt((delta ** 2).sum(axis=(0, 2)))", "np.sqrt(np.abs(delta.sum(axis=(0, 2))))"),
 }
 
 

@@ -6,7 +6,7 @@ format's precision u (fp16: 2^-11, bf16: 2^-8, relative); with two GEMM
 stages the spectrum's RMS relative error is about u.  The hi+lo split leaves
 about u^2 plus FP32 accumulation.  Bounds on the RMS error relative to the
 oracle spectrum's RMS: fp16 2e-3, bf16 1.5e-2, fp16 split 5e-6, bf16 split
-1e-4 (measured values are printed)."""
+1e-4 (measured values are printed); every element within 6 times that."""
 import numpy as np
 import pytest
 
@@ -19,6 +19,7 @@ from rxgen import C4, make_frames  # noqa: E402
 from tests.parity import as_complex, check_bits, check_H, check_xhat  # noqa: E402
 
 MODES = {"f16": (1, 2e-3), "bf16": (2, 1.5e-2), "f16_split": (3, 5e-6), "bf16_split": (4, 1e-4)}
+ELEM_FACTOR = 6.0
 
 
 @pytest.fixture(scope="module")
@@ -54,8 +55,14 @@ def test_fft_error_within_the_format_bound(rx, mode, kind):
     ref = oracle.fft_symbols(iq, fr.pilot, **_kw(SMALL))
     rms = np.sqrt(np.mean(np.abs(ref) ** 2, axis=-1))
     err = np.sqrt(np.mean(np.abs(Y - ref) ** 2, axis=-1)) / rms
-    print(f"[mfma] {mode} {kind}: RMS relative error max {err.max():.3e}, mean {err.mean():.3e}", flush=True)
+    elem = np.abs(Y - ref) / rms[..., None]
+    print(f"[mfma] {mode} {kind}: RMS relative error max {err.max():.3e}, mean {err.mean():.3e}; "
+          f"element max {elem.max():.3e}", flush=True)
     assert err.max() <= bound
+    # per element: the error of one bin is a sum of many independent operand
+    # roundings (near Gaussian), so over 2048 bins its maximum stays within
+    # about 4.5 standard deviations of the RMS
+    assert elem.max() <= ELEM_FACTOR * bound
 
 
 def test_split_f16_path_meets_the_fp32_parity_bar(rx):
@@ -99,8 +106,10 @@ def test_path_error_follows_the_fft_error(rx, mode):
     # equalised symbols: both H and Y carry the FFT error (about 2 x bound relative)
     x = as_complex(xhat)
     rel = np.sqrt(np.mean(np.abs(x - ref.xhat) ** 2)) / np.sqrt(np.mean(np.abs(ref.xhat) ** 2))
-    print(f"[mfma] {mode}: x-hat RMS relative error {rel:.3e}", flush=True)
+    elem = np.abs(x - ref.xhat) / np.maximum(1.0, np.abs(ref.xhat))
+    print(f"[mfma] {mode}: x-hat RMS relative error {rel:.3e}, element max {elem.max():.3e}", flush=True)
     assert rel <= 4 * bound
+    assert elem.max() <= ELEM_FACTOR * 4 * bound
     hrel = np.sqrt(np.mean(np.abs(as_complex(H) - ref.H) ** 2) / np.mean(np.abs(ref.H) ** 2))
     assert hrel <= 2 * bound
 

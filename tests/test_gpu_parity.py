@@ -221,3 +221,29 @@ def test_full_size_c2_launch_all_slots_checked(rx):
     check_H(as_complex(H), ref.H[src])
     check_xhat(as_complex(xhat), ref.xhat[src])
     check_bits(bits.cpu().numpy(), ref.bits[src], ref.xhat[src], cfg.bits_per_sym)
+
+
+@pytest.mark.parametrize("fft_mode", [0, 3])
+def test_full_size_c4_launch_all_slots_checked(rx, fft_mode):
+    """The largest configured shape (128 antennas, N=2048, 64-QAM, 500 slots,
+    7.86 GB of input: offsets past 4 GiB), with the FP32 radix FFT and with the
+    fp16 hi+lo DFT-GEMM FFT.  Eight distinct generated slots are tiled over the
+    500 on the device; every output element is checked against the oracle of
+    its source slot."""
+    cfg = C4
+    _say("full-size", cfg.name, "S", cfg.n_slots, "fft_mode", fft_mode)
+    uniq = make_frames(cfg, n_slots=8)
+    ref = oracle.process_frame(uniq.iq, uniq.pilot, n_threads=8, **_kw(cfg))
+    S = cfg.n_slots
+    src = np.arange(S) % 8
+    iq = torch.from_numpy(uniq.iq).cuda()[torch.from_numpy(src).cuda()].contiguous()
+    assert iq.numel() * 2 > 4 * 2 ** 30
+    plan = rx.Plan.from_config(cfg, uniq.pilot, fft_mode=fft_mode)
+    H, xhat, bits = plan.process(iq, want_H=True)
+    torch.cuda.synchronize()
+    del iq
+    for c0 in range(0, S, 50):
+        sl = slice(c0, min(S, c0 + 50))
+        check_H(as_complex(H[sl]), ref.H[src[sl]])
+    check_xhat(as_complex(xhat), ref.xhat[src])
+    check_bits(bits.cpu().numpy(), ref.bits[src], ref.xhat[src], cfg.bits_per_sym)

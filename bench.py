@@ -5,12 +5,21 @@ One step = ``rx_process_frame`` over every slot of the workload (the estimate
 and demod kernels), with the int16 input already resident in HBM.  Prints one
 JSON line.  Defaults: the 64-antenna, N=1024, 200-slot workload, 1 GPU.
 
-    python bench.py [--steps K] [--warmup W] [--workload c2|c1|c4] [--no-cpu]
+    python bench.py [--steps K] [--warmup W] [--workload c2|c1|c4|sweep|batch|denoiser|sync|precision]
+                    [--no-cpu] [--workers P]
+
+Timing: W untimed steps, then untimed steps until the clocks have settled
+(windows of 20 steps, at least 200 ms, two windows within 2 %; reported as
+warmup_ms / warmup_settle_steps), then exactly K timed steps with an event
+after each (ms_per_step over all K, step_ms_median and step_ms_min).
 
 Besides the headline it reports, for the dominant kernel (demod), algorithmic
-bytes per launch / its average HIP-event-timed duration against the 8 TB/s
-HBM peak; the FP64 oracle timed on the host cores on the same workload; and
-LS NMSE, BER and EVM at 20 dB SNR.
+bytes per launch (payload samples without CP, x-hat and bits; the channel
+estimate's read is listed apart) over its average HIP-event-timed duration,
+against the 8 TB/s HBM peak and a device copy measured in the same run; the
+FP64 oracle timed on every usable host CPU and on one thread, with the CPU
+model; and LS NMSE, BER and EVM at 20 dB SNR.  ``--workload sweep`` runs the
+antenna-count x FFT-length sweep (N = 64, 1024; 1..128 antennas).
 """
 from __future__ import annotations
 
@@ -27,8 +36,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X, published (with packed FP32)
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1901_07499_amd", "csrc", f)
-                  for f in ("rx_kernels.hip", "rx_fft.hpp", "rx_comb.hpp")]
+CSRC = os.path.join(ROOT, "paper_1901_07499_amd", "csrc")
+KERNEL_SOURCES = sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC)
+                        if f.endswith((".hip", ".hpp", ".cpp", ".h")))
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_demod_c2.json")
 
 
@@ -45,18 +55,132 @@ def kernel_hash() -> str:
 
 def algorithmic_bytes(cfg, S: int, part: str) -> int:
     """Bytes the method must move: payload samples (no CP) of the symbols a
-    call reads, the outputs it writes, and the channel estimate when it is an
-    input or output of the call.  Excludes CP samples and any re-reads."""
+    call reads and the outputs it writes.  Excludes CP samples, re-reads and
+    the channel estimate, which the method need not move through HBM (the
+    estimate's own output and the demod's read of it are the "h" part,
+    reported beside the roofline)."""
     A, N, U, T, b = cfg.n_ant, cfg.fft_len, cfg.n_used, cfg.n_sym, cfg.bits_per_sym
     Td = T - 1
     out = Td * U * 8 + Td * U * b // 8       # x-hat (complex64) + packed bits
-    if part == "path":                        # whole path, H kept internal
+    if part == "path":                        # whole path
         return S * (T * A * N * 4 + out)
-    if part == "demod":                       # data symbols + H in, outputs
-        return S * (Td * A * N * 4 + A * U * 8 + out)
-    if part == "estimate":                    # pilot symbol in, H out
-        return S * (A * N * 4 + A * U * 8)
+    if part == "demod":                       # data symbols in, outputs
+        return S * (Td * A * N * 4 + out)
+    if part == "estimate":                    # pilot symbol in
+        return S * (A * N * 4)
+    if part == "h":                           # one pass of the estimate over HBM
+        return S * (A * U * 8)
     raise ValueError(part)
+
+
+def host_cpus():
+    """CPUs this process may run on (affinity), capped by a cgroup CPU quota
+    when one is set, and the CPU model name."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    quota = None
+    try:
+        q, p = open("/sys/fs/cgroup/cpu.max").read().split()[:2]
+        if q != "max":
+            quota = float(q) / float(p)
+    except (OSError, ValueError):
+        pass
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    usable = n if quota is None else max(1, min(n, int(quota)))
+    return usable, {"affinity_cpus": n, "cgroup_cpu_quota": quota, "model": model}
+
+
+def time_oracle(fr, cfg, threads: int, budget_s: float):
+    """The FP64 oracle over a bounded prefix of the workload's slots on
+    `threads` threads: the slot count is grown until one pass takes about
+    budget_s / 3, then passes repeat until budget_s.  Returns
+    (antenna-samples/s, slots per pass, seconds per pass)."""
+    import oracle
+    S = fr.iq.shape[0]
+    n = max(1, min(S, threads))
+    while True:
+        t0 = time.perf_counter()
+        oracle.run_config(fr, n_threads=threads, slots=slice(0, n))
+        dt = time.perf_counter() - t0
+        if dt >= budget_s / 3 or n == S:
+            break
+        n = min(S, max(n + 1, int(n * min(8.0, budget_s / 3 / max(dt, 1e-4)))))
+    reps, total = 1, dt
+    while total < budget_s and reps < 100:
+        t0 = time.perf_counter()
+        oracle.run_config(fr, n_threads=threads, slots=slice(0, n))
+        total += time.perf_counter() - t0
+        reps += 1
+    per_pass = total / reps
+    return n * cfg.n_sym * cfg.n_ant * (cfg.fft_len + cfg.cp_len) / per_pass, n, per_pass
+
+
+def cpu_baseline(fr, cfg, budget_s: float = 8.0):
+    """The oracle on every usable host CPU and on one thread (the paper's
+    CPU baseline is one core), same int16 slots as the GPU run."""
+    threads, info = host_cpus()
+    v_all, n_all, dt_all = time_oracle(fr, cfg, threads, budget_s)
+    v_one, n_one, dt_one = time_oracle(fr, cfg, 1, budget_s)
+    log(f"cpu baseline {v_all:.4e} antenna-samples/s on {threads} threads, {v_one:.4e} on 1 ({info['model']})")
+    return {"value": v_all, "unit": "antenna-samples/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n_all} of {fr.iq.shape[0]} slots of {cfg.name}, FP64 C oracle, {threads} threads, "
+                      f"{dt_all:.3f} s per pass, passes repeated for ~{budget_s:g} s",
+            "cpu_model": info["model"], "affinity_cpus": info["affinity_cpus"],
+            "cgroup_cpu_quota": info["cgroup_cpu_quota"],
+            "single_thread": {"value": v_one, "unit": "antenna-samples/s", "cores": 1,
+                              "sample": f"first {n_one} slots, {dt_one:.3f} s per pass"}}
+
+
+def settle(step, min_ms: float = 200.0, max_ms: float = 3000.0, window: int = 20):
+    """Untimed steps after the fixed warm-up until the clocks have settled:
+    windows of `window` steps are timed with events until at least min_ms
+    have passed and two consecutive windows agree within 2 %.  Returns
+    (ms spent, steps run, last window's ms per step)."""
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    spent, steps, prev = 0.0, 0, None
+    while True:
+        e0.record()
+        for _ in range(window):
+            step()
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        spent += ms
+        steps += window
+        cur = ms / window
+        if (spent >= min_ms and prev is not None and abs(cur - prev) <= 0.02 * prev) or spent >= max_ms:
+            return spent, steps, cur
+        prev = cur
+
+
+def copy_peak_gbps(nbytes: int = 1 << 30, reps: int = 10):
+    """Device-to-device copy rate (bytes read + written per second), the
+    measured second denominator of the HBM fraction."""
+    import torch
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
 COPY_BYTES = 1 << 30
@@ -112,7 +236,8 @@ def bench_batch(args):
     import numpy as np
     from rxgen import make_batch
     t0 = time.time()
-    bt = make_batch(args.frames, BATCH_SEED, workers=min(16, os.cpu_count() or 1))
+    workers = args.workers if args.workers > 0 else min(16, os.cpu_count() or 1)
+    bt = make_batch(args.frames, BATCH_SEED, workers=workers)
     log(f"generated batch of {args.frames} frames: {bt.iq.nbytes / 1e6:.1f} MB in {time.time() - t0:.1f} s")
     import torch
     from paper_1901_07499_amd import rx
@@ -449,13 +574,103 @@ def bench_precision(args):
     print(json.dumps(rec), flush=True)
 
 
+def bench_sweep(args):
+    """Antenna-count x FFT-length sweep: N = 64 and 1024 at 1..128 antennas,
+    14 symbols per slot, each point ~1 GiB of int16 input resident in HBM
+    (distinct generated slots tiled over the buffer).  Per point: the whole
+    path's throughput, algorithmic bytes against the HBM peak, time per OFDM
+    symbol (every antenna), and the FP64 oracle on one host thread beside it."""
+    import math
+    import numpy as np
+    from rxgen import SWEEP_ANTENNAS, SWEEP_FFT_LENS, make_frames, sweep_config
+    workers = args.workers if args.workers > 0 else min(16, os.cpu_count() or 1)
+    points = [(n, a) for n in SWEEP_FFT_LENS for a in SWEEP_ANTENNAS]
+    if args.sweep_points:
+        points = [tuple(int(x) for x in p.split("x")) for p in args.sweep_points.split(",")]
+    # Generate every point's distinct slots before the process touches the GPU.
+    frames = {}
+    t0 = time.time()
+    for n, a in points:
+        cfg = sweep_config(n, a)
+        k = min(cfg.n_slots, max(8, math.ceil(args.sweep_unique_mb * 2 ** 20 / cfg.slot_bytes)))
+        frames[(n, a)] = (cfg, make_frames(cfg, n_slots=k, workers=workers))
+    log(f"generated {len(points)} sweep points in {time.time() - t0:.1f} s")
+    cpu_rates = {}
+    if not args.no_cpu:
+        for p in points:
+            cfg, fr = frames[p]
+            cpu_rates[p] = time_oracle(fr, cfg, 1, args.sweep_cpu_s)
+    import torch
+    from paper_1901_07499_amd import rx
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    copy_gbs = copy_peak_gbps()
+    rows = []
+    for p in points:
+        cfg, fr = frames[p]
+        S, k = cfg.n_slots, fr.iq.shape[0]
+        uniq = torch.from_numpy(fr.iq).to(dev)
+        iq = uniq[torch.arange(S, device=dev) % k].contiguous()
+        del uniq
+        plan = rx.Plan.from_config(cfg, fr.pilot)
+        Td = cfg.n_sym - 1
+        out = (None, torch.empty((S, Td, cfg.n_used, 2), dtype=torch.float32, device=dev),
+               torch.empty((S, Td, plan.row_bytes), dtype=torch.uint8, device=dev))
+        ws = torch.empty(max(256, plan.workspace_bytes(S)), dtype=torch.uint8, device=dev)
+
+        def step():
+            plan.process(iq, out=out, workspace=ws)
+
+        for _ in range(args.warmup):
+            step()
+        settle(step, min_ms=100.0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            step()
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        samples = S * cfg.n_sym * cfg.n_ant * (cfg.fft_len + cfg.cp_len)
+        alg = algorithmic_bytes(cfg, S, "path")
+        gbs = alg / (ms * 1e-3) / 1e9
+        row = {"fft_len": cfg.fft_len, "n_ant": cfg.n_ant, "n_slots": S, "distinct_slots": k,
+               "input_MB": round(S * cfg.slot_bytes / 1e6, 1), "ms_per_step": round(ms, 5),
+               "antenna_samples_per_s": samples / (ms * 1e-3),
+               "us_per_ofdm_symbol": round(ms * 1e3 / (S * cfg.n_sym), 6),
+               "algorithmic_GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+               "copy_frac": round(gbs / copy_gbs, 4)}
+        if p in cpu_rates:
+            v1, n1, dt1 = cpu_rates[p]
+            row["oracle_1thread_antenna_samples_per_s"] = v1
+            row["oracle_1thread_sample"] = f"first {n1} slots, {dt1:.3f} s per pass"
+            row["gpu_over_oracle_1thread"] = round(row["antenna_samples_per_s"] / v1, 1)
+        log(f"N={cfg.fft_len} A={cfg.n_ant} S={S}: {ms:.4f} ms, {row['antenna_samples_per_s']:.3e} "
+            f"antenna-samples/s, {row['hbm_frac'] * 100:.1f} % HBM")
+        rows.append(row)
+        del iq, out, ws, plan
+        torch.cuda.empty_cache()
+    head = next((r for r in rows if r["fft_len"] == 1024 and r["n_ant"] == 64), rows[-1])
+    threads, info = host_cpus()
+    rec = {"metric": "antenna-samples/s through FFT+LS+demod, % HBM peak, over antennas x FFT length",
+           "value": head["antenna_samples_per_s"], "unit": "antenna-samples/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "sweep", "value_point": f"N={head['fft_len']} A={head['n_ant']}",
+                      "fft_len": sorted({r["fft_len"] for r in rows}), "n_ant": sorted({r["n_ant"] for r in rows}),
+                      "n_sym": 14, "input_per_point": "~1 GiB int16 IQ resident in HBM"},
+           "copy_peak_GBps": round(copy_gbs, 1), "cpu_model": info["model"], "points": rows,
+           "kernel_hash": kernel_hash()}
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     # about 50 ms of untimed work first: the GPU's clocks settle within ~100 steps
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4", "batch", "denoiser", "sync", "precision"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4", "batch", "denoiser", "sync", "precision", "sweep"])
     ap.add_argument("--frames", type=int, default=256, help="frames of the batch workload")
     ap.add_argument("--slots", type=int, default=None,
                     help="slots of the denoiser (default 32), sync (32) and precision (500, its configuration) workloads")
@@ -466,8 +681,12 @@ def main():
     ap.add_argument("--dn-rows", type=int, default=1024, help="rows (antenna estimates) per training step")
     ap.add_argument("--dn-lr", type=float, default=2e-3, help="Adam learning rate")
     ap.add_argument("--workers", type=int, default=0,
-                    help="generator processes for the denoiser and precision workloads (0 = up to 16; "
-                         "1 under a profiler)")
+                    help="generator processes of every workload (0 = up to 16; 1 under a profiler)")
+    ap.add_argument("--sweep-points", default="",
+                    help="sweep points as NxA, comma separated (default: N in {64, 1024} x A in {1..128})")
+    ap.add_argument("--sweep-unique-mb", type=float, default=16.0,
+                    help="MiB of distinct generated slots per sweep point (tiled to ~1 GiB)")
+    ap.add_argument("--sweep-cpu-s", type=float, default=1.0, help="seconds of one-thread oracle per sweep point")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-quality", action="store_true", help="skip the 20 dB quality figures")
     ap.add_argument("--gen-unique", type=int, default=0,
@@ -503,10 +722,13 @@ def main():
     if args.workload == "precision":
         bench_precision(args)
         return
+    if args.workload == "sweep":
+        bench_sweep(args)
+        return
     from rxgen import C1, C2, C2_20DB, C4, make_frames
     cfg = {"c1": C1, "c2": C2, "c4": C4}[args.workload]
     S = cfg.n_slots
-    workers = min(16, os.cpu_count() or 1)
+    workers = args.workers if args.workers > 0 else min(16, os.cpu_count() or 1)
 
     # Generate every input before the process touches the GPU (fork-based pool).
     t0 = time.time()
@@ -556,41 +778,65 @@ def main():
     ws = torch.empty(plan.workspace_bytes(S), dtype=torch.uint8, device=dev)
     out = (None, xhat, bits)
 
-    for _ in range(args.warmup):
+    def step():
         plan.process(iq, out=out, workspace=ws)
-    torch.cuda.synchronize()
-    log(f"warmup {args.warmup} done")
 
-    t_start, t_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(args.warmup):
+        step()
     torch.cuda.synchronize()
-    t_start.record()
-    for _ in range(args.steps):
-        plan.process(iq, out=out, workspace=ws)
-    t_end.record()
+    # The GPU's clocks take ~100 ms of load to settle: keep stepping (untimed)
+    # until the step time is steady.
+    settle_ms, settle_steps, settle_last = settle(step)
+    log(f"warmup {args.warmup} steps, then {settle_steps} settling steps in {settle_ms:.1f} ms "
+        f"(last window {settle_last:.4f} ms/step)")
+
+    # Timed region: exactly K steps; an event between steps gives per-step times.
+    ev_steps = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
-    ms_per_step = t_start.elapsed_time(t_end) / args.steps
+    ev_steps[0].record()
+    for k in range(args.steps):
+        step()
+        ev_steps[k + 1].record()
+    torch.cuda.synchronize()
+    ms_per_step = ev_steps[0].elapsed_time(ev_steps[-1]) / args.steps
+    import statistics
+    step_ms = [ev_steps[k].elapsed_time(ev_steps[k + 1]) for k in range(args.steps)]
     samples_per_step = S * cfg.n_sym * cfg.n_ant * (cfg.fft_len + cfg.cp_len)
     value = samples_per_step / (ms_per_step * 1e-3)
-    log(f"timed {args.steps} steps: {ms_per_step:.4f} ms/step, {value:.4e} antenna-samples/s")
+    log(f"timed {args.steps} steps: {ms_per_step:.4f} ms/step (median {statistics.median(step_ms):.4f}, "
+        f"min {min(step_ms):.4f}), {value:.4e} antenna-samples/s")
 
-    # Per-kernel durations over the same work: events around each launch on the launch stream.
+    # Per-kernel durations over the same work: each kernel launched `reps`
+    # times back to back between two events on the launch stream (an event
+    # between every pair of launches would add its own gap to each).
     H = torch.empty((S, cfg.n_ant, cfg.n_used, 2), dtype=torch.float32, device=dev)
     reps = max(args.steps, 10)
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(reps)]
-    for r in range(reps):
-        ev[r][0].record()
-        plan.estimate(iq, H=H)
-        ev[r][1].record()
-        st = rx.rx_demod(plan._plan, iq.data_ptr(), H.data_ptr(), S, xhat.data_ptr(), bits.data_ptr(), None,
-                         torch.cuda.current_stream().cuda_stream)
-        assert st == rx.RX_OK
-        ev[r][2].record()
-    torch.cuda.synchronize()
-    est_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / reps
-    dem_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / reps
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def est_launch():
+        assert rx.rx_estimate(plan._plan, iq.data_ptr(), S, H.data_ptr(), None, None, stream) == rx.RX_OK
+
+    def dem_launch():
+        assert rx.rx_demod(plan._plan, iq.data_ptr(), H.data_ptr(), S, xhat.data_ptr(), bits.data_ptr(), None,
+                           stream) == rx.RX_OK
+
+    def per_launch(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fn()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    est_ms = per_launch(est_launch)
+    dem_ms = per_launch(dem_launch)
     dem_bytes = algorithmic_bytes(cfg, S, "demod")
     achieved = dem_bytes / (dem_ms * 1e-3) / 1e9
     log(f"estimate {est_ms:.4f} ms, demod {dem_ms:.4f} ms -> demod {achieved:.1f} GB/s algorithmic")
+    copy_gbs = copy_peak_gbps()
+    log(f"device copy {copy_gbs:.1f} GB/s")
 
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
@@ -600,7 +846,9 @@ def main():
     roofline = {"bound": "hbm", "kernel": "demod_kernel", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "algorithmic_bytes_per_launch": dem_bytes,
-                "avg_launch_ms": round(dem_ms, 5)}
+                "avg_launch_ms": round(dem_ms, 5),
+                "h_read_bytes_per_launch": algorithmic_bytes(cfg, S, "h"),
+                "copy_peak_GBps": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
     # The same kernel against the FP32 vector peak: algorithmic flops are 5 N log2 N per transform
     # plus 12 per used subcarrier and antenna for conj(H) Y and |H|^2 (packed FP32 is not used, so
     # the reachable vector rate is half of the published peak).
@@ -632,25 +880,7 @@ def main():
                    "ber": nerr / nbits, "ber_95_upper": (3.0 / nbits if nerr == 0 else None)}
         log(f"quality at 20 dB: {quality}")
 
-    cpu = None
-    if not args.no_cpu:
-        import oracle
-        threads = min(16, os.cpu_count() or 1)
-        n_cpu = S
-        t0 = time.perf_counter()
-        oracle.run_config(fr, n_threads=threads, slots=slice(0, n_cpu))
-        dt = time.perf_counter() - t0
-        if dt < 10.0 and n_cpu == S:   # repeat the pass to reach a stable ~10 s sample
-            reps_cpu = max(1, int(10.0 / max(dt, 1e-3)))
-            t0 = time.perf_counter()
-            for _ in range(reps_cpu):
-                oracle.run_config(fr, n_threads=threads)
-            dt = (time.perf_counter() - t0) / reps_cpu
-        cpu_value = n_cpu * cfg.n_sym * cfg.n_ant * (cfg.fft_len + cfg.cp_len) / dt
-        cpu = {"value": cpu_value, "unit": "antenna-samples/s", "cores": threads, "kind": "oracle",
-               "sample": f"all {n_cpu} slots of {cfg.name}, FP64 C oracle, {threads} threads, "
-                         f"{dt:.3f} s per pass"}
-        log(f"cpu baseline {cpu_value:.4e} antenna-samples/s on {threads} threads")
+    cpu = None if args.no_cpu else cpu_baseline(fr, cfg)
 
     rec = {
         "metric": "antenna-samples/s through FFT+LS+demod, % HBM peak; BER/NMSE at 20 dB vs plain",
@@ -673,6 +903,11 @@ def main():
         "alu_view": alu_view,
         "path_algorithmic_GBps": round(path_gbs, 1),
         "path_hbm_frac": round(path_gbs / HBM_PEAK_GBS, 4),
+        "path_copy_frac": round(path_gbs / copy_gbs, 4),
+        "step_ms_median": round(statistics.median(step_ms), 5),
+        "step_ms_min": round(min(step_ms), 5),
+        "warmup_ms": round(settle_ms, 1),
+        "warmup_settle_steps": settle_steps,
         "estimate_ms": round(est_ms, 5),
         "demod_ms": round(dem_ms, 5),
         "h2d_ms_pinned": round(h2d_ms, 3),

@@ -100,6 +100,29 @@ C5_20DB = C5.replace(name="c5_A128_N2048_comb4_20dB", snr_db=(20.0, 20.0), seed=
 
 CONFIGS = {c.name: c for c in (C1, C2, C2_20DB, C4, C5, C5_20DB)}
 
+# Antenna-count x FFT-length sweep: Table I's two FFT lengths (64 with a
+# 16-sample CP, 1024 with 72) at 1..16 receive antennas, extended to 128;
+# 14 symbols per slot (1 pilot + 13 data).  N = 64 carries 52 used
+# subcarriers of QPSK at the paper's 10 MHz; N = 1024 the C2 shape (600 used,
+# 16-QAM, 15.36 MS/s).  Channel and SNR as C2 (delays clamped to the CP).
+SWEEP_ANTENNAS = (1, 2, 4, 8, 16, 32, 64, 128)
+SWEEP_FFT_LENS = (64, 1024)
+
+
+def sweep_config(fft_len: int, n_ant: int, target_bytes: int = 1 << 30) -> FrameConfig:
+    """One sweep point, with enough slots that the int16 input fills
+    ``target_bytes`` (rounded up to a whole slot)."""
+    if fft_len == 64:
+        cp, used, b, fs = 16, 52, 2, 10e6
+    elif fft_len == 1024:
+        cp, used, b, fs = 72, 600, 4, 15.36e6
+    else:
+        raise ValueError("the sweep covers FFT lengths 64 and 1024")
+    i = SWEEP_FFT_LENS.index(fft_len) * len(SWEEP_ANTENNAS) + SWEEP_ANTENNAS.index(n_ant)
+    cfg = C2.replace(name=f"sweep_N{fft_len}_A{n_ant}", n_ant=n_ant, fft_len=fft_len, cp_len=cp, n_used=used,
+                     bits_per_sym=b, fs_hz=fs, seed=SEED_BASE + 100 + i)
+    return cfg.replace(n_slots=-(-target_bytes // cfg.slot_bytes))
+
 
 def used_subcarrier_bins(fft_len: int, n_used: int) -> np.ndarray:
     """FFT bin of each used subcarrier, in ascending signed frequency.

@@ -71,7 +71,9 @@ enum rx_status {
   RX_E_UNSUPPORTED = -2, /* valid but not implemented: N not a power of two in 64..2048,
                             bits_per_sym not in {2,4,6}, more than one user, unknown combiner */
   RX_E_HIP = -3,         /* a HIP runtime call or kernel launch failed */
-  RX_E_NOMEM = -4        /* device or host allocation failed */
+  RX_E_NOMEM = -4,       /* device or host allocation failed */
+  RX_E_SCRATCH = -5      /* the call needs more than the library's fixed scratch
+                            (rx_process_frame_noalloc) */
 };
 
 enum rx_combiner { RX_COMB_MRC = 0, RX_COMB_ZF = 1 };
@@ -149,6 +151,22 @@ int rx_demod(rx_plan_t plan, const int16_t* iq, const float* H, int64_t n_slots,
  * xhat and bits optional but not both NULL. */
 int rx_process_frame(rx_plan_t plan, const int16_t* iq, int64_t n_slots, float* H, float* xhat,
                      uint8_t* bits, void* workspace, void* hip_stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the whole
+ * path of rx_process_frame without H or workspace arguments; nothing is
+ * allocated.  The channel estimate is kept in a library-owned device array of
+ * RX_NOALLOC_SCRATCH_BYTES on each GPU the library runs on, held until the
+ * process ends, and the slots go through in chunks whose estimates fit it
+ * (one launch pair per chunk; results equal rx_process_frame's).  One slot's
+ * estimate, A*U*8 bytes, must fit, else RX_E_SCRATCH.  Every call on a GPU
+ * shares that GPU's array: calls that overlap on one GPU (different streams,
+ * or host threads) race and must be serialised by the caller.  The array
+ * needs no clearing (each chunk's estimate is written before it is read).
+ * xhat and bits optional but not both NULL. */
+#define RX_NOALLOC_SCRATCH_BYTES (64u << 20)
+int rx_process_frame_noalloc(rx_plan_t plan, const int16_t* iq, int64_t n_slots, float* xhat, uint8_t* bits,
+                             void* hip_stream);
 
 /* CP removal + FFT only, for every symbol of every antenna:
  * Y float [S][T][A][N][2] in natural bin order.  For validating the FFT stage. */

@@ -42,7 +42,7 @@ def build(verbose: bool = False, save_temps: str | None = None) -> str:
             o = os.path.join(tmp, name + ".o")
             _run([cc, *COMMON, f"--offload-arch={ARCH}", "-c", os.path.join(CSRC, name + ".cpp"), "-o", o], verbose)
             objs.append(o)
-        for name in ("rx_denoise", "rx_sync", "rx_mfma_fft"):
+        for name in ("rx_denoise", "rx_sync", "rx_mfma_fft", "rx_noalloc"):
             o = os.path.join(tmp, name + ".o")
             _run([cc, *COMMON, f"--offload-arch={ARCH}", *DEVICE_FLAGS, "-x", "hip", "-c",
                   os.path.join(CSRC, name + ".hip"), "-o", o], verbose)

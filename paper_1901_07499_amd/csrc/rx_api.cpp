@@ -226,8 +226,43 @@ const char* rx_status_string(int status) {
     case RX_E_UNSUPPORTED: return "unsupported parameters";
     case RX_E_HIP: return "HIP runtime error";
     case RX_E_NOMEM: return "out of memory";
+    case RX_E_SCRATCH: return "one slot's channel estimate exceeds the library's fixed scratch";
     default: return "unknown status";
   }
 }
 
 }  // extern "C"
+
+namespace rx {
+
+// The whole path with the channel estimate kept in a fixed device buffer of
+// hbuf_bytes: slots are processed in chunks whose estimates fit it, each
+// chunk's estimate written before its demod reads it (one stream, so chunk
+// k + 1 overwrites the buffer only after chunk k's demod).  Checks come
+// first; nothing is allocated.
+int process_frame_in(rx_plan_t plan, const int16_t* iq, int64_t n_slots, float* xhat, uint8_t* bits,
+                     float2* hbuf, size_t hbuf_bytes, void* hip_stream) {
+  int st = check_call(plan, iq, n_slots);
+  if (st != RX_OK || n_slots == 0) return st;
+  if (!xhat && !bits) return RX_E_INVALID_ARG;
+  if (xhat && !aligned(xhat, 8)) return RX_E_INVALID_ARG;
+  const size_t per_slot = (size_t)plan->p.n_ant * plan->p.n_used * sizeof(float2);
+  if (per_slot > hbuf_bytes) return RX_E_SCRATCH;
+  if ((st = check_device(plan)) != RX_OK) return st;
+  if (!hbuf) return RX_E_HIP;
+  const int64_t chunk = (int64_t)(hbuf_bytes / per_slot);
+  const int64_t slot_iq = (int64_t)plan->p.n_sym * plan->p.n_ant * (plan->p.fft_len + plan->p.cp_len) * 2;
+  const int64_t Td = plan->p.n_sym - 1;
+  const int64_t row_bytes = (int64_t)plan->p.n_used * plan->p.bits_per_sym / 8;
+  for (int64_t s0 = 0; s0 < n_slots; s0 += chunk) {
+    const int64_t S = n_slots - s0 < chunk ? n_slots - s0 : chunk;
+    const rx::LaunchArgs la = launch_args(plan, iq + s0 * slot_iq, S, hip_stream);
+    if ((st = hip_status(rx::launch_estimate(la, hbuf))) != RX_OK) return st;
+    float2* x = xhat ? reinterpret_cast<float2*>(xhat) + s0 * Td * plan->p.n_used : nullptr;
+    uint8_t* b = bits ? bits + s0 * Td * row_bytes : nullptr;
+    if ((st = hip_status(rx::launch_demod(la, plan->p.combiner == RX_COMB_ZF, hbuf, x, b))) != RX_OK) return st;
+  }
+  return RX_OK;
+}
+
+}  // namespace rx

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+struct rx_plan_s;
+
 namespace rx {
 
 struct LaunchArgs {
@@ -27,6 +29,10 @@ hipError_t launch_estimate(const LaunchArgs& la, float2* H);
 hipError_t launch_g(const LaunchArgs& la, const float2* H, float* g);
 hipError_t launch_demod(const LaunchArgs& la, bool zf, const float2* H, float2* xhat, uint8_t* bits);
 hipError_t launch_fft(const LaunchArgs& la, float2* Y);
+// rx_process_frame with the estimate in a fixed buffer, slots in chunks that
+// fit it (rx_api.cpp); returns an rx_status.
+int process_frame_in(::rx_plan_s* plan, const int16_t* iq, int64_t n_slots, float* xhat, uint8_t* bits,
+                     float2* hbuf, size_t hbuf_bytes, void* hip_stream);
 
 // ---- batches of frames with mixed shapes (one slot per frame)
 // Device descriptor of one frame; offsets index the packed batch buffers.

@@ -17,14 +17,15 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librx.so")
 
-RX_OK, RX_E_INVALID_ARG, RX_E_UNSUPPORTED, RX_E_HIP, RX_E_NOMEM = 0, -1, -2, -3, -4
+RX_OK, RX_E_INVALID_ARG, RX_E_UNSUPPORTED, RX_E_HIP, RX_E_NOMEM, RX_E_SCRATCH = 0, -1, -2, -3, -4, -5
+RX_NOALLOC_SCRATCH_BYTES = 64 << 20
 RX_COMB_MRC, RX_COMB_ZF = 0, 1
 RX_FFT_RADIX_F32, RX_FFT_MFMA_F16, RX_FFT_MFMA_BF16, RX_FFT_MFMA_F16_SPLIT, RX_FFT_MFMA_BF16_SPLIT = 0, 1, 2, 3, 4
 FFT_MODES = {"f32": 0, "f16": 1, "bf16": 2, "f16_split": 3, "bf16_split": 4}
 
 # Every symbol the header declares; the CPU test checks they are all exported.
 EXPORTS = ("rx_params_check", "rx_plan_create", "rx_plan_destroy", "rx_workspace_bytes", "rx_estimate",
-           "rx_demod", "rx_process_frame", "rx_debug_fft", "rx_status_string",
+           "rx_demod", "rx_process_frame", "rx_process_frame_noalloc", "rx_debug_fft", "rx_status_string",
            "rx_batch_create", "rx_batch_destroy", "rx_batch_layout", "rx_batch_workspace_bytes",
            "rx_batch_process", "rx_batch_autotune", "rx_batch_config", "rx_batch_schedules", "rx_batch_set_config",
            "rx_fft_radices", "rx_batch_frame_latency",
@@ -76,6 +77,7 @@ def _load() -> ctypes.CDLL:
     lib.rx_estimate.argtypes = [vp, vp, i64, vp, vp, vp, vp]
     lib.rx_demod.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp]
     lib.rx_process_frame.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp]
+    lib.rx_process_frame_noalloc.argtypes = [vp, vp, i64, vp, vp, vp]
     lib.rx_debug_fft.argtypes = [vp, vp, i64, vp, vp]
     lib.rx_status_string.argtypes = [ctypes.c_int]
     lib.rx_status_string.restype = ctypes.c_char_p
@@ -150,6 +152,10 @@ def rx_demod(plan, iq, H, n_slots, xhat, bits, workspace, stream) -> int:
 
 def rx_process_frame(plan, iq, n_slots, H, xhat, bits, workspace, stream) -> int:
     return _lib.rx_process_frame(plan, iq, n_slots, H, xhat, bits, workspace, stream)
+
+
+def rx_process_frame_noalloc(plan, iq, n_slots, xhat, bits, stream) -> int:
+    return _lib.rx_process_frame_noalloc(plan, iq, n_slots, xhat, bits, stream)
 
 
 def rx_debug_fft(plan, iq, n_slots, Y, stream) -> int:

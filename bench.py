@@ -46,9 +46,26 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def kernel_hash() -> str:
+# Library sources each workload's kernels are built from (the launchers and
+# API files included); "all" is the whole library.
+WORKLOAD_SOURCES = {
+    "path": ("rx_kernels.hip", "rx_fft.hpp", "rx_comb.hpp", "rx_launch.h", "rx_api.cpp"),
+    "batch": ("rx_kernels.hip", "rx_fft.hpp", "rx_comb.hpp", "rx_launch.h", "rx_batch.cpp"),
+    "denoiser": ("rx_denoise.hip", "rx_dn_api.cpp", "rx_comb.hpp", "rx_launch.h", "rx_kernels.hip", "rx_fft.hpp",
+                 "rx_api.cpp"),
+    "mfma": ("rx_mfma_fft.hip", "rx_kernels.hip", "rx_fft.hpp", "rx_launch.h", "rx_api.cpp"),
+    "sync": ("rx_sync.hip", "rx_sync_api.cpp", "rx_kernels.hip", "rx_fft.hpp", "rx_launch.h", "rx_api.cpp"),
+}
+
+
+def kernel_hash(part: str = "all") -> str:
+    """sha256 prefix of the library sources behind a workload's kernels
+    (every source for "all"): ties a profile or counter file to the code it
+    measured."""
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    files = KERNEL_SOURCES if part == "all" else [os.path.join(CSRC, f) for f in sorted(WORKLOAD_SOURCES[part])]
+    for p in files:
+        h.update(os.path.basename(p).encode())
         h.update(open(p, "rb").read())
     return h.hexdigest()[:16]
 
@@ -217,7 +234,7 @@ def write_traffic(demod_fetch, demod_write, copy_fetch, copy_write):
     kw = COPY_BYTES / cw
     df = _counter_per_dispatch(demod_fetch, "demod_kernel", "FETCH_SIZE") * 1024 * kf
     dw = _counter_per_dispatch(demod_write, "demod_kernel", "WRITE_SIZE") * 1024 * kw
-    rec = {"workload": C2.name, "kernel": "demod_kernel", "kernel_hash": kernel_hash(),
+    rec = {"workload": C2.name, "kernel": "demod_kernel", "kernel_hash": kernel_hash("path"),
            "fetch_bytes": df, "write_bytes": dw, "bytes_per_launch": df + dw,
            "fetch_scale": kf, "write_scale": kw,
            "algorithmic_bytes_per_launch": algorithmic_bytes(C2, C2.n_slots, "demod")}
@@ -284,7 +301,7 @@ def bench_batch(args):
                                   "demod_radices": list(rx.fft_radices(n, sd)),
                                   "est_radices": list(rx.fft_radices(n, se))}
                          for n, (w, j, sd, se) in chosen.items()},
-           "kernel_hash": kernel_hash()}
+           "kernel_hash": kernel_hash("batch"), "library_hash": kernel_hash()}
     print(json.dumps(rec), flush=True)
 
 
@@ -406,7 +423,7 @@ def bench_denoiser(args):
                         "slots_equivalent": rows_trained / A, "ms": round(train_ms, 1),
                         "rows_per_s": rows_trained / (train_ms * 1e-3), "lr": args.dn_lr,
                         "loss_first_100": float(lc[:100].mean()), "loss_last_100": float(lc[-100:].mean())},
-           "quality": quality, "kernel_hash": kernel_hash()}
+           "quality": quality, "kernel_hash": kernel_hash("denoiser"), "library_hash": kernel_hash()}
     print(json.dumps(rec), flush=True)
 
 
@@ -502,7 +519,7 @@ def bench_sync(args):
            "sync_find_ms": round(find_ms, 5), "extract_ms": round(ext_ms, 5),
            "extract_GBps": round(ext_bytes / (ext_ms * 1e-3) / 1e9, 1),
            "offset": int(off.item()), "lead": lead, "bit_errors": errs, "bits": int(sent.size),
-           "kernel_hash": kernel_hash()}
+           "kernel_hash": kernel_hash("sync"), "library_hash": kernel_hash()}
     print(json.dumps(rec), flush=True)
 
 
@@ -570,7 +587,7 @@ def bench_precision(args):
            "dtype": "f16 MFMA with hi+lo split, f32 accumulate", "data": "synthetic",
            "config": {"workload": C4.name, "n_ant": A, "fft_len": N, "cp_len": CP, "n_used": U, "n_sym": T,
                       "bits_per_sym": B, "n_slots": S, "quality_slots": args.quality_slots},
-           "modes": out, "kernel_hash": kernel_hash()}
+           "modes": out, "kernel_hash": kernel_hash("mfma"), "library_hash": kernel_hash()}
     print(json.dumps(rec), flush=True)
 
 
@@ -660,7 +677,7 @@ def bench_sweep(args):
                       "fft_len": sorted({r["fft_len"] for r in rows}), "n_ant": sorted({r["n_ant"] for r in rows}),
                       "n_sym": 14, "input_per_point": "~1 GiB int16 IQ resident in HBM"},
            "copy_peak_GBps": round(copy_gbs, 1), "cpu_model": info["model"], "points": rows,
-           "kernel_hash": kernel_hash()}
+           "kernel_hash": kernel_hash("path"), "library_hash": kernel_hash()}
     print(json.dumps(rec), flush=True)
 
 
@@ -841,7 +858,7 @@ def main():
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         t = json.load(open(TRAFFIC_FILE))
-        if t.get("kernel_hash") == kernel_hash() and t.get("workload") == cfg.name:
+        if t.get("kernel_hash") == kernel_hash("path") and t.get("workload") == cfg.name:
             traffic = t.get("bytes_per_launch")
     roofline = {"bound": "hbm", "kernel": "demod_kernel", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -913,7 +930,7 @@ def main():
         "h2d_ms_pinned": round(h2d_ms, 3),
         "h2d_inclusive_antenna_samples_per_s": samples_per_step / ((ms_per_step + h2d_ms) * 1e-3),
         "quality_20db": quality,
-        "kernel_hash": kernel_hash(),
+        "kernel_hash": kernel_hash("path"), "library_hash": kernel_hash(),
     }
     print(json.dumps(rec), flush=True)
 

@@ -534,7 +534,13 @@ def bench_precision(args):
     workers = args.workers if args.workers > 0 else min(16, os.cpu_count() or 1)
     S = args.slots
     t0 = time.time()
-    fr = make_frames(C4, n_slots=S, workers=workers)
+    if args.gen_unique > 0:
+        import dataclasses
+        k = min(args.gen_unique, S)
+        fr = make_frames(C4, n_slots=k)
+        fr = dataclasses.replace(fr, iq=np.ascontiguousarray(fr.iq[np.arange(S) % k]))
+    else:
+        fr = make_frames(C4, n_slots=S, workers=workers)
     qual = {snr: make_frames(C4.replace(name=f"c4_{snr:g}dB", snr_db=(snr, snr), seed=C4.seed + int(snr)),
                              n_slots=args.quality_slots, workers=workers) for snr in (10.0, 20.0, 30.0)}
     log(f"generated {S} slots of {C4.name} ({fr.iq.nbytes / 1e6:.1f} MB) and quality sets in {time.time() - t0:.1f} s")
@@ -586,7 +592,8 @@ def bench_precision(args):
            "ms_per_step": best["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f16 MFMA with hi+lo split, f32 accumulate", "data": "synthetic",
            "config": {"workload": C4.name, "n_ant": A, "fft_len": N, "cp_len": CP, "n_used": U, "n_sym": T,
-                      "bits_per_sym": B, "n_slots": S, "quality_slots": args.quality_slots},
+                      "bits_per_sym": B, "n_slots": S, "quality_slots": args.quality_slots,
+                      "distinct_slots": min(args.gen_unique, S) if args.gen_unique > 0 else S},
            "modes": out, "kernel_hash": kernel_hash("mfma"), "library_hash": kernel_hash()}
     print(json.dumps(rec), flush=True)
 
@@ -708,7 +715,7 @@ def main():
     ap.add_argument("--no-quality", action="store_true", help="skip the 20 dB quality figures")
     ap.add_argument("--gen-unique", type=int, default=0,
                     help="generate only this many distinct slots in this process and tile them over the "
-                         "workload (for profiler runs, where no worker processes may be started)")
+                         "workload (for profiler runs, where no worker processes may be started; c1, c2, c4, precision)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy (reference for the traffic counters)")
     ap.add_argument("--write-traffic", nargs=4, metavar=("DEMOD_FETCH", "DEMOD_WRITE", "COPY_FETCH", "COPY_WRITE"),
@@ -792,11 +799,24 @@ def main():
     Td = cfg.n_sym - 1
     xhat = torch.empty((S, Td, cfg.n_used, 2), dtype=torch.float32, device=dev)
     bits = torch.empty((S, Td, plan.row_bytes), dtype=torch.uint8, device=dev)
-    ws = torch.empty(plan.workspace_bytes(S), dtype=torch.uint8, device=dev)
-    out = (None, xhat, bits)
+    H = torch.empty((S, cfg.n_ant, cfg.n_used, 2), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream().cuda_stream
 
-    def step():
-        plan.process(iq, out=out, workspace=ws)
+    # One step = the path's two launches through the C ABI, rx_estimate into H
+    # then rx_demod from it (the kernels rx_process_frame launches for a batch
+    # whose H fits its workspace), with events on the launch stream before,
+    # between and after them: the timed region itself gives the step time and
+    # each kernel's duration.
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record()
+        assert rx.rx_estimate(plan._plan, iq.data_ptr(), S, H.data_ptr(), None, None, stream) == rx.RX_OK
+        if ev is not None:
+            ev[1].record()
+        assert rx.rx_demod(plan._plan, iq.data_ptr(), H.data_ptr(), S, xhat.data_ptr(), bits.data_ptr(), None,
+                           stream) == rx.RX_OK
+        if ev is not None:
+            ev[2].record()
 
     for _ in range(args.warmup):
         step()
@@ -807,51 +827,36 @@ def main():
     log(f"warmup {args.warmup} steps, then {settle_steps} settling steps in {settle_ms:.1f} ms "
         f"(last window {settle_last:.4f} ms/step)")
 
-    # Timed region: exactly K steps; an event between steps gives per-step times.
-    ev_steps = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    # Timed region: exactly K steps, three events each.
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     torch.cuda.synchronize()
-    ev_steps[0].record()
     for k in range(args.steps):
-        step()
-        ev_steps[k + 1].record()
+        step(evs[k])
     torch.cuda.synchronize()
-    ms_per_step = ev_steps[0].elapsed_time(ev_steps[-1]) / args.steps
+    ms_per_step = evs[0][0].elapsed_time(evs[-1][2]) / args.steps
     import statistics
-    step_ms = [ev_steps[k].elapsed_time(ev_steps[k + 1]) for k in range(args.steps)]
+    step_ms = [e[0].elapsed_time(e[2]) for e in evs]
+    est_each = [e[0].elapsed_time(e[1]) for e in evs]
+    dem_each = [e[1].elapsed_time(e[2]) for e in evs]
     samples_per_step = S * cfg.n_sym * cfg.n_ant * (cfg.fft_len + cfg.cp_len)
     value = samples_per_step / (ms_per_step * 1e-3)
     log(f"timed {args.steps} steps: {ms_per_step:.4f} ms/step (median {statistics.median(step_ms):.4f}, "
         f"min {min(step_ms):.4f}), {value:.4e} antenna-samples/s")
-
-    # Per-kernel durations over the same work: each kernel launched `reps`
-    # times back to back between two events on the launch stream (an event
-    # between every pair of launches would add its own gap to each).
-    H = torch.empty((S, cfg.n_ant, cfg.n_used, 2), dtype=torch.float32, device=dev)
-    reps = max(args.steps, 10)
-    stream = torch.cuda.current_stream().cuda_stream
-
-    def est_launch():
-        assert rx.rx_estimate(plan._plan, iq.data_ptr(), S, H.data_ptr(), None, None, stream) == rx.RX_OK
-
-    def dem_launch():
-        assert rx.rx_demod(plan._plan, iq.data_ptr(), H.data_ptr(), S, xhat.data_ptr(), bits.data_ptr(), None,
-                           stream) == rx.RX_OK
-
-    def per_launch(fn):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        fn()
-        e0.record()
-        for _ in range(reps):
-            fn()
-        e1.record()
-        e1.synchronize()
-        return e0.elapsed_time(e1) / reps
-
-    est_ms = per_launch(est_launch)
-    dem_ms = per_launch(dem_launch)
+    est_ms = sum(est_each) / len(est_each)
+    dem_ms = sum(dem_each) / len(dem_each)
+    # the same batch through the boundary's one-call entry point, for comparison
+    ws = torch.empty(plan.workspace_bytes(S), dtype=torch.uint8, device=dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        plan.process(iq, out=(None, xhat, bits), workspace=ws)
+    e1.record()
+    e1.synchronize()
+    process_ms = e0.elapsed_time(e1) / args.steps
     dem_bytes = algorithmic_bytes(cfg, S, "demod")
     achieved = dem_bytes / (dem_ms * 1e-3) / 1e9
-    log(f"estimate {est_ms:.4f} ms, demod {dem_ms:.4f} ms -> demod {achieved:.1f} GB/s algorithmic")
+    log(f"estimate {est_ms:.4f} ms, demod {dem_ms:.4f} ms (means over the timed steps) -> demod {achieved:.1f} GB/s "
+        f"algorithmic; rx_process_frame {process_ms:.4f} ms per step")
     copy_gbs = copy_peak_gbps()
     log(f"device copy {copy_gbs:.1f} GB/s")
 
@@ -927,6 +932,8 @@ def main():
         "warmup_settle_steps": settle_steps,
         "estimate_ms": round(est_ms, 5),
         "demod_ms": round(dem_ms, 5),
+        "demod_ms_median": round(statistics.median(dem_each), 5),
+        "process_frame_ms_per_step": round(process_ms, 5),
         "h2d_ms_pinned": round(h2d_ms, 3),
         "h2d_inclusive_antenna_samples_per_s": samples_per_step / ((ms_per_step + h2d_ms) * 1e-3),
         "quality_20db": quality,

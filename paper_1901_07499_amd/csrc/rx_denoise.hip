@@ -24,8 +24,8 @@
 // whole rows; a row is cut into tiles of TO = 240 output positions.  Each
 // tile recomputes a halo (3 positions per layer and side), so the layers of
 // a tile run back to back out of LDS: x0 [pos][2], then x1, x2, x3 in two
-// [pos][40] bf16 ping-pong buffers (32 channels + 8 pad: 80-byte rows make
-// the 16-byte operand reads of 8 consecutive positions conflict-free).  A
+// [pos][40] bf16 ping-pong buffers (32 channels + 8 pad; the row pitch is
+// discussed at RS below).  A
 // GEMM unit is 16 positions x 32 output channels (two MFMA rows of 16); the
 // K dimension is (tap, input channel): one 16-byte LDS read per tap.  The
 // last layer (2 output channels) puts its 7 taps into the MFMA rows instead
@@ -61,6 +61,15 @@ typedef uint16_t bfbits;  // raw bf16
 constexpr int kBlock = 256;
 constexpr int TO = 240;    // output positions per tile
 constexpr int NPOS = 288;  // LDS positions per activation buffer
+// Row pitch of the activation buffers.  gfx950's LDS has 64 banks of 4
+// bytes; probes of the bank-conflict counter show that a 16-byte read is
+// served 16 lanes at a time, each group of 16 taking lanes from two
+// quarter-waves (for example lanes 0-7 with 24-31), while 8-byte accesses are
+// served 32 lanes at a time.  For the operand reads (lane (r, q): 16 bytes at
+// row r, slot q) a pitch of 20 dwords (80 bytes) then gives two-way conflicts
+// and a pitch of 24 dwords none; but at 24 the unit stores (8 bytes, rows r,
+// slots q) conflict two-way instead, and the 96-byte pitch measured 3 %
+// slower over 4096 rows, so the buffers keep 80-byte rows.
 constexpr int RS = 40;     // bf16 per LDS position row (32 channels + 8 pad)
 constexpr int BASE_F = 12; // forward: LDS index of position t0
 constexpr int BASE_B = 18; // backward: LDS index of position t0
@@ -262,8 +271,12 @@ __device__ __forceinline__ void layer32_pipelined(const bfbits* __restrict__ X, 
 // what the next layer needs for the final 240 outputs (layer 3 also reads up
 // to 6 stale positions past x2's range; they reach only discarded outputs).
 // Layer 1's K = 32 slots are (tap 0..15, channel 0..1) with taps 7..15 zero.
+// The register budget of two wavefronts per SIMD is stated: left to itself
+// the compiler took 225 VGPRs + 32 AGPRs for the inference instance (one
+// wavefront per SIMD), which ran 0.34 ms for 4096 rows against 0.19 ms with
+// the budget (256 VGPRs, a 12-byte spill).
 template <bool TRAIN>
-__global__ __launch_bounds__(kBlock) void dn_forward_kernel(const float2* __restrict__ Hin, int64_t rows, int U,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void dn_forward_kernel(const float2* __restrict__ Hin, int64_t rows, int U,
                                                             const bf16x8* __restrict__ frag,
                                                             const float* __restrict__ theta,
                                                             float2* __restrict__ Hout, DnTrainIo io) {

@@ -200,57 +200,127 @@ __global__ __launch_bounds__(64 * W) void estimate_kernel(const uint32_t* __rest
                          ps);
 }
 
-// Uniform slots, one transform per wavefront (N = 1024): a grid of resident
-// workgroups only; transform g of the grid (G in all) takes jobs g, g + G, ...
-// of the S*A list of (slot, antenna) pilot symbols, the next job's samples
-// requested before the current transform.  Every wavefront then ends within
-// one job of the others, where (slot, group) workgroups leave a partial last
-// round of workgroups running alone whenever their count exceeds what the
-// GPU holds at once (c2: 3200 wavefronts against 3072 resident).
+// Uniform slots, transforms within one wavefront (N <= 1024): a grid of
+// resident workgroups only; transform slot g of the grid (G in all) takes jobs
+// g, g + G, ... of the S*A list of (slot, antenna) pilot symbols, the next
+// job's samples requested before the current transform.  Every wavefront then
+// ends within one job of the others, where (slot, group) workgroups leave a
+// partial last round of workgroups running alone whenever their count exceeds
+// what the GPU holds at once (c2: 3200 wavefronts against 3072 resident), and
+// short transforms of small antenna counts would leave most slots idle.  The
+// F slots of a wavefront hold consecutive jobs; the loop runs while the
+// wavefront's first job exists, and a slot past the end transforms the last
+// job's samples and stores nothing.
 template <int N, int W>
 __global__ __launch_bounds__(64 * W) void estimate_grid_kernel(const uint32_t* __restrict__ iq, int64_t S, int A,
                                                                int T, int CP, int U, const float2* __restrict__ tw,
                                                                const float2* __restrict__ pf,
                                                                float2* __restrict__ H, int ps) {
   using Sh = FftShape<N>;
-  static_assert(Sh::F == 1 && Sh::WPT == 1, "one transform per wavefront");
+  static_assert(Sh::WPT == 1, "a transform within one wavefront");
   extern __shared__ float2 lds[];
   __shared__ float2 twtab[FftTwiddles<N>::kLdsFloat2 > 0 ? FftTwiddles<N>::kLdsFloat2 : 1];
   FftTwiddles<N> twr;
   tile_setup<N>(twr, twtab, tw);
-  const int li = threadIdx.x & 63;
+  const int li = threadIdx.x % Sh::L, ts = threadIdx.x / Sh::L;
+  const int f = ts % Sh::F;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t jobs = S * A;
-  const int64_t G = (int64_t)gridDim.x * W;
-  int64_t j = (int64_t)blockIdx.x * W + wave;  // uniform over the wavefront
-  if (j >= jobs) return;                       // no workgroup barrier below
+  const int64_t G = (int64_t)gridDim.x * W * Sh::F;
+  int64_t j0 = ((int64_t)blockIdx.x * W + wave) * Sh::F;  // the wavefront's first job (uniform)
+  if (j0 >= jobs) return;                                 // no workgroup barrier below
   EstLane<N> el;
   el.init(li, U, pf);
-  // (slot, antenna) of job j, advanced by G per step without a division
+  // (slot, antenna) of this slot's job j, advanced by G per step without a
+  // division (meaningless once j is past the list: the last job is read)
+  int64_t j = j0 + f;
   const int Gs = (int)(G / A), Ga = (int)(G % A);
   int64_t s = j / A;
   int a = (int)(j - s * A);
-  auto rec = [&](int64_t ss, int aa) { return iq + (ss * T * A + aa) * (int64_t)(N + CP) + CP; };
-  float2* buf = lds + wave * Lds<N>::kSlot;
+  auto rec = [&](int64_t jj, int64_t ss, int aa) {
+    if (jj >= jobs) {
+      ss = S - 1;
+      aa = A - 1;
+    }
+    return iq + (ss * T * A + aa) * (int64_t)(N + CP) + CP;
+  };
+  float2* buf = lds + ts * Lds<N>::kSlot;
   uint32_t nxt[Sh::P];
-  load_symbol<N>(nxt, rec(s, a), li, true);
-  for (; j < jobs; j += G) {
+  load_symbol<N>(nxt, rec(j, s, a), li, true);
+  for (; j0 < jobs; j0 += G) {
     float2 v[Sh::P];
     unpack_symbol<N>(v, nxt);
-    const int64_t s0 = s;
+    const int64_t s0 = s, jcur = j;
     const int a0 = a;
+    j += G;
     s += Gs;
     a += Ga;
     if (a >= A) {
       a -= A;
       s++;
     }
-    if (j + G < jobs) load_symbol<N>(nxt, rec(s, a), li, true);
-    estimate_job<N>(v, el, buf, li, twr, H + (s0 * A + a0) * (int64_t)U, U, ps);
+    if (j0 + G < jobs) load_symbol<N>(nxt, rec(j, s, a), li, true);
+    estimate_job<N>(v, el, buf, li, twr, jcur < jobs ? H + (s0 * A + a0) * (int64_t)U : nullptr, U, ps);
   }
 }
 
 // ------------------------------------------------------------------ demod
+// Hard decisions of one equalized symbol x (paper Sec. II-C, demodulation):
+// per-axis Gray decisions, B bits in the order b0 (Re sign), b1 (Im sign),
+// then the amplitude bits of Re and Im alternately, MSB first.  Strict
+// comparisons, so ties and -0.0 give 0.
+__device__ __forceinline__ uint32_t qam_code(float2 x, int B) {
+  const float c16 = 3.16227766016837933f;  // sqrt(10)
+  const float c64 = 6.48074069840786023f;  // sqrt(42)
+  uint32_t br[3], bi[3];
+  br[0] = x.x < 0.f;
+  bi[0] = x.y < 0.f;
+  if (B == 4) {
+    br[1] = fabsf(x.x) * c16 > 2.f;
+    bi[1] = fabsf(x.y) * c16 > 2.f;
+  } else if (B == 6) {
+    const float ur = fabsf(x.x) * c64, ui = fabsf(x.y) * c64;
+    br[1] = ur > 4.f;
+    bi[1] = ui > 4.f;
+    br[2] = fabsf(ur - 4.f) > 2.f;
+    bi[2] = fabsf(ui - 4.f) > 2.f;
+  }
+  uint32_t acc = 0;
+  for (int j = 0; j < B / 2; j++) acc = (acc << 2) | (br[j] << 1) | bi[j];
+  return acc;
+}
+
+// Output of subcarriers 4 qd .. 4 qd + 3 (fewer at the end of the row) of one
+// data symbol: sum(d, z, g) adds the partial sums of subcarrier d to z and g
+// (ZF: z is already the equalized symbol); x = z / g (0 when g = 0), then the
+// decisions, packed MSB-first (4 symbols = B/2 bytes).  xrow, brow: the
+// symbol's output rows, or null.
+template <bool ZF, typename SumF>
+__device__ __forceinline__ void finish_quad(int qd, int U, int B, SumF sum, float2* __restrict__ xrow,
+                                            uint8_t* __restrict__ brow) {
+  const int nsym = min(4, U - 4 * qd);
+  uint32_t acc = 0;  // bits of up to 4 symbols, MSB-first
+  for (int e = 0; e < nsym; e++) {
+    const int d = 4 * qd + e;
+    float2 zz = make_float2(0.f, 0.f);
+    float gg = 0.f;
+    sum(d, zz, gg);
+    float2 x;
+    if constexpr (ZF) {
+      x = zz;
+    } else {
+      x = gg > 0.f ? make_float2(zz.x / gg, zz.y / gg) : make_float2(0.f, 0.f);
+    }
+    if (xrow) xrow[d] = x;
+    acc = (acc << B) | qam_code(x, B);
+  }
+  if (brow) {
+    const int nbits = nsym * B;  // a multiple of 8
+    uint8_t* o = brow + (qd * B) / 2;
+    for (int byte = 0; byte < nbits / 8; byte++) o[byte] = (uint8_t)(acc >> (nbits - 8 * (byte + 1)));
+  }
+}
+
 // One slot as seen by the per-tile routines (pointers already offset to the
 // slot; outputs may be null).
 struct SlotView {
@@ -454,56 +524,19 @@ __device__ __forceinline__ void demod_tile(const SlotView& sv, int t, float2* ld
   }
   __syncthreads();
 
-  const int row_bytes = U * B / 8;
   const int64_t out_row = t - 1;
-  float2* xhat = sv.xhat;
-  uint8_t* bits = sv.bits;
-  const float c16 = 3.16227766016837933f;  // sqrt(10)
-  const float c64 = 6.48074069840786023f;  // sqrt(42)
-  for (int qd = threadIdx.x; 4 * qd < U; qd += 64 * W) {
-    const int nsym = min(4, U - 4 * qd);
-    uint32_t acc = 0;  // bits of up to 4 symbols, MSB-first
-    for (int e = 0; e < nsym; e++) {
-      const int d = 4 * qd + e;
-      float2 zz = make_float2(0.f, 0.f);
-      float gg = 0.f;
+  const int nq = (U + 3) / 4;
+  for (int qd = threadIdx.x; qd < nq; qd += 64 * W) {
+    finish_quad<ZF>(qd, U, B, [&](int d, float2& zz, float& gg) {
       for (int w = 0; w < ROWS; w++) {
         const float2 p = rz[w * U + d];
         zz.x += p.x;
         zz.y += p.y;
         if constexpr (!ZF) gg += rg[w * U + d];
       }
-      float2 x;
-      if constexpr (ZF) {
-        x = zz;
-      } else {
-        x = gg > 0.f ? make_float2(zz.x / gg, zz.y / gg) : make_float2(0.f, 0.f);
-      }
-      if (xhat) xhat[out_row * U + d] = x;
-      // hard decisions: strict comparisons, so ties and -0.0 give 0
-      uint32_t br[3], bi[3];
-      br[0] = x.x < 0.f;
-      bi[0] = x.y < 0.f;
-      if (B == 4) {
-        br[1] = fabsf(x.x) * c16 > 2.f;
-        bi[1] = fabsf(x.y) * c16 > 2.f;
-      } else if (B == 6) {
-        const float ur = fabsf(x.x) * c64, ui = fabsf(x.y) * c64;
-        br[1] = ur > 4.f;
-        bi[1] = ui > 4.f;
-        br[2] = fabsf(ur - 4.f) > 2.f;
-        bi[2] = fabsf(ui - 4.f) > 2.f;
-      }
-      for (int j = 0; j < B / 2; j++) acc = (acc << 2) | (br[j] << 1) | bi[j];
-    }
-    if (bits) {
-      const int nbits = nsym * B;                                // a multiple of 8
-      uint8_t* o = bits + out_row * row_bytes + (qd * B) / 2;   // 4 symbols = B/2 bytes
-      for (int byte = 0; byte < nbits / 8; byte++) o[byte] = (uint8_t)(acc >> (nbits - 8 * (byte + 1)));
-    }
+    }, sv.xhat ? sv.xhat + out_row * U : nullptr, sv.bits ? sv.bits + out_row * (U * B / 8) : nullptr);
   }
 }
-
 
 // Where the uniform demod keeps the last pass's twiddles: in VGPRs (no LDS
 // reads in the antenna loop) for N = 1024 and 2048 at the widest spectrum
@@ -541,13 +574,174 @@ void demod_kernel(const uint32_t* __restrict__ iq, int64_t S, int A, int T, int 
   demod_tile<N, QH, W, ZF>(sv, t, lds, twr);
 }
 
+// Several (slot, data symbol) items per workgroup, for transforms shorter than
+// a wavefront (F > 1 per wavefront) and for antenna counts too small to share
+// among the W wavefronts of one item.  A workgroup takes IPW = F * W / Wa
+// consecutive items: Wa wavefronts (1, 2 or 4) share an item's antennas
+// (wavefront w takes antennas w % Wa, w % Wa + Wa, ...), and transform slot f
+// of wavefront w serves item (w / Wa) * F + f of the workgroup, so one job of
+// a wavefront is one antenna of F items.  Each item's Wa partial sums meet in
+// LDS rows (row = transform slot, as in demod_tile); x-hat, decisions and
+// bits follow per item (paper Sec. II-C, MRC paragraph).
+template <int N, int QH, int W, bool ZF>
+__global__ __launch_bounds__(64 * W) void demod_items_kernel(const uint32_t* __restrict__ iq, int64_t S, int A,
+                                                             int T, int CP, int U, int B,
+                                                             const float2* __restrict__ tw,
+                                                             const float2* __restrict__ H,
+                                                             float2* __restrict__ xhat, uint8_t* __restrict__ bits,
+                                                             int Wa) {
+  using Sh = FftShape<N>;
+  static_assert(Sh::WPT == 1, "a transform within one wavefront");
+  constexpr int NI = 2 * QH;
+  static_assert(NI <= Sh::P, "window wider than the lane's spectrum");
+  using Tw = FftTwiddles<N, 0, demod_twiddles_in_lds<N, QH>()>;
+  extern __shared__ float2 lds[];
+  __shared__ float2 twtab[Tw::kLdsFloat2 > 0 ? Tw::kLdsFloat2 : 1];
+  Tw twr;
+  tile_setup(twr, twtab, tw);
+
+  const int Td = T - 1;
+  const int64_t items = S * Td;
+  const int IPW = (W / Wa) * Sh::F;
+  const int64_t item0 = xcd_remap(blockIdx.x, gridDim.x) * IPW;
+  const int li = threadIdx.x % Sh::L, ts = threadIdx.x / Sh::L;
+  const int f = ts % Sh::F;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int sub = wave % Wa;
+  // item of this transform slot (uniform over the wavefront when F == 1); a
+  // slot past the last item reads the last item's data and stores nothing
+  const int64_t item = item0 + (wave / Wa) * Sh::F + f;
+  const int64_t ic = item < items ? item : items - 1;
+  const int64_t s = ic / Td;
+  const int t = 1 + (int)(ic - s * Td);
+  const uint32_t* sym = iq + (s * T + t) * (int64_t)A * (N + CP) + CP;  // antenna 0 of symbol t
+  const float2* Hs = H + s * A * (int64_t)U;
+
+  // Spectrum window as in demod_tile: window register i holds spectrum
+  // register qof(i), subcarrier li + doff(i) when wok(i); channel loads use
+  // that index clamped into [0, U).
+  const int hU = U >> 1;
+  auto qof = [](int i) { return i < QH ? i : Sh::P - NI + i; };
+  auto doff = [&](int i) { return Sh::L * qof(i) + (i < QH ? hU - 1 : hU - N); };
+  auto wok = [&](int i) {
+    const int k = li + Sh::L * qof(i);
+    return i < QH ? (k >= 1 && k <= hU) : (k >= N - hU);
+  };
+  auto dcl = [&](int i) { return min(max(li + doff(i), 0), U - 1); };
+  float2 z[NI];
+  float g[NI];
+#pragma unroll
+  for (int i = 0; i < NI; i++) {
+    z[i] = make_float2(0.f, 0.f);
+    g[i] = 0.f;
+  }
+  if constexpr (ZF) {
+    for (int a = 0; a < A; a++) {
+#pragma unroll
+      for (int i = 0; i < NI; i++) {
+        const float2 h = Hs[(int64_t)a * U + dcl(i)];
+        g[i] = fmaf(h.x, h.x, fmaf(h.y, h.y, g[i]));
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NI; i++) g[i] = g[i] > 0.f ? 1.0f / g[i] : 0.f;  // now 1/g
+  }
+  // F == 1: the slot's estimate through a buffer resource (uniform base,
+  // row offset in a scalar register, loop-invariant lane offsets)
+  const __amdgpu_buffer_rsrc_t hrs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<float2*>(Hs), (short)0, A * U * 8, 0x00020000);
+  int hoff[NI];
+#pragma unroll
+  for (int i = 0; i < NI; i++) hoff[i] = dcl(i) * 8;
+
+  float2* bufs[1] = {lds + ts * Lds<N>::kSlot};
+  float2* const(&buf)[1] = bufs;
+  uint32_t nxt[Sh::P];
+  if (sub < A) load_symbol<N>(nxt, sym + (int64_t)sub * (N + CP), li, true);
+  for (int a = sub; a < A; a += Wa) {  // uniform over the wavefront
+    float2 v[1][Sh::P];
+    unpack_symbol<N>(v[0], nxt);
+    fft_first_pass<N, 1>(v, buf, li);
+    float2 hv[NI];
+    if constexpr (Sh::F == 1) {
+      const int so = a * (U * 8);
+#pragma unroll
+      for (int i = 0; i < NI; i++)
+        hv[i] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(hrs, hoff[i], so, 0));
+    } else {
+      const float2* hrow = Hs + (int64_t)a * U;
+#pragma unroll
+      for (int i = 0; i < NI; i++) hv[i] = hrow[dcl(i)];
+    }
+    if (a + Wa < A) load_symbol<N>(nxt, sym + (int64_t)(a + Wa) * (N + CP), li, true);
+    fft_rest<N, 1>(v, buf, li, twr);
+#pragma unroll
+    for (int i = 0; i < NI; i++) {
+      const float2 y = v[0][Spectrum<N, 0>::reg(qof(i))];
+      const float2 hh = hv[i];
+      if constexpr (ZF) {
+        const float2 w = make_float2(hh.x * g[i], -hh.y * g[i]);  // conj(h) / g
+        z[i].x = fmaf(w.x, y.x, fmaf(-w.y, y.y, z[i].x));
+        z[i].y = fmaf(w.x, y.y, fmaf(w.y, y.x, z[i].y));
+      } else {
+        z[i].x = fmaf(hh.x, y.x, fmaf(hh.y, y.y, z[i].x));  // conj(h) * y
+        z[i].y = fmaf(hh.x, y.y, fmaf(-hh.y, y.x, z[i].y));
+        g[i] = fmaf(hh.x, hh.x, fmaf(hh.y, hh.y, g[i]));
+      }
+    }
+    exchange_fence<N>();  // this job's LDS reads precede the next job's writes
+  }
+
+  // Partial sums of every transform slot to its LDS row, then per item the
+  // sum over its Wa rows in a fixed order.
+  constexpr int ROWS = W * Sh::F;
+  __syncthreads();
+  float2* rz = lds;                                      // [ROWS][U]
+  float* rg = reinterpret_cast<float*>(lds + ROWS * U);  // [ROWS][U]
+#pragma unroll
+  for (int i = 0; i < NI; i++) {
+    if (wok(i)) {
+      rz[ts * U + li + doff(i)] = z[i];
+      if constexpr (!ZF) rg[ts * U + li + doff(i)] = g[i];
+    }
+  }
+  __syncthreads();
+  const int nq = (U + 3) / 4;
+  const int row_bytes = U * B / 8;
+  for (int u = threadIdx.x; u < IPW * nq; u += 64 * W) {
+    const int litem = u / nq, qd = u - litem * nq;
+    const int64_t it = item0 + litem;
+    if (it >= items) break;  // items past the end lie at the end of u's range
+    const int row0 = (litem / Sh::F) * Wa * Sh::F + litem % Sh::F;  // row of wavefront sub 0
+    finish_quad<ZF>(qd, U, B, [&](int d, float2& zz, float& gg) {
+      for (int k = 0; k < Wa; k++) {
+        const int r = row0 + k * Sh::F;
+        const float2 p = rz[r * U + d];
+        zz.x += p.x;
+        zz.y += p.y;
+        if constexpr (!ZF) gg += rg[r * U + d];
+      }
+    }, xhat ? xhat + it * U : nullptr, bits ? bits + it * row_bytes : nullptr);
+  }
+}
+
 // ------------------------------------------------------------------ batches
 // Persistent kernels for a batch of frames sharing one FFT length: each
 // workgroup repeatedly takes the next tile from a device work queue (tiles
 // are numbered in frame order) and looks its frame up in a tile->frame map.
+// Thread 0 first stamps the completion of the workgroup's previous tile when
+// it was the last data symbol of its frame (done_index >= 0: the frame's
+// completion counter reaches done_last; 100 MHz device clock), then takes the
+// next tile.  Doing both here, before the barrier, keeps every path through
+// the caller's tile loop uniform (a divergent step at the end of the loop body
+// lets the compiler split the loop around its barriers).
 __device__ __forceinline__ int next_tile(int* queue, int n_tiles, const int* tile_frame, int* tile_sh,
-                                         int* frame_sh, int& frame) {
+                                         int* frame_sh, int& frame, int* done_count = nullptr,
+                                         unsigned long long* done_time = nullptr, int done_index = -1,
+                                         int done_last = 0) {
   if (threadIdx.x == 0) {
+    if (done_index >= 0 && atomicAdd(done_count + done_index, 1) == done_last)
+      done_time[done_index] = __builtin_amdgcn_s_memrealtime();
     const int tile = atomicAdd(queue, 1);
     *tile_sh = tile;
     *frame_sh = tile < n_tiles ? tile_frame[tile] : -1;
@@ -596,9 +790,11 @@ __global__ __launch_bounds__(64 * W) void batch_demod_kernel(const FrameDesc* __
   __shared__ int tile_sh, frame_sh;
   Tw twr;
   tile_setup<N>(twr, twtab, tw);
+  int done_index = -1, done_last = 0;  // the previous tile's frame, stamped by next_tile
   for (;;) {
     int frame;
-    const int tile = next_tile(queue, n_tiles, tile_frame, &tile_sh, &frame_sh, frame);
+    const int tile = next_tile(queue, n_tiles, tile_frame, &tile_sh, &frame_sh, frame, done_count, done_time,
+                               done_index, done_last);
     if (tile >= n_tiles) break;
     const FrameDesc d = fd[frame];
     SlotView sv;
@@ -609,8 +805,8 @@ __global__ __launch_bounds__(64 * W) void batch_demod_kernel(const FrameDesc* __
     sv.A = d.A; sv.T = d.T; sv.CP = d.CP; sv.U = d.U; sv.B = d.B;
     demod_tile<N, QH, W, false>(sv, 1 + tile - d.dem_tile0, lds, twr);
     __syncthreads();  // outputs written and LDS free before the next tile
-    if (threadIdx.x == 0 && atomicAdd(done_count + d.index, 1) == d.T - 2)
-      done_time[d.index] = __builtin_amdgcn_s_memrealtime();  // last data symbol of the frame
+    done_index = d.index;
+    done_last = d.T - 2;  // the frame's last data symbol completes it
   }
 }
 
@@ -725,11 +921,14 @@ int estimate_grid_capacity(size_t lds) {
 
 template <int N>
 hipError_t estimate_n(const LaunchArgs& la, float2* H) {
-  if constexpr (FftShape<N>::F == 1 && FftShape<N>::WPT == 1) {
+  if constexpr (FftShape<N>::WPT == 1) {
     const size_t lds = fft_lds_bytes<N, kWavesEst>();
+    hipError_t e = allow_lds(estimate_grid_kernel<N, kWavesEst>, lds);
+    if (e != hipSuccess) return e;
     const int resident = estimate_grid_capacity<N, kWavesEst>(lds);
     if (resident <= 0) return hipErrorInvalidValue;
-    const int64_t needed = (la.S * la.A + kWavesEst - 1) / kWavesEst;
+    constexpr int per_group = transforms_per_group<N, kWavesEst>();
+    const int64_t needed = (la.S * la.A + per_group - 1) / per_group;
     const int64_t grid = needed < resident ? needed : resident;
     hipLaunchKernelGGL((estimate_grid_kernel<N, kWavesEst>), dim3((unsigned)grid), dim3(64 * kWavesEst), lds,
                        la.stream, la.iq, la.S, la.A, la.T, la.CP, la.U, la.tw, la.pf, H, la.ps);
@@ -758,10 +957,39 @@ hipError_t fft_n(const LaunchArgs& la, float2* Y) {
   return hipGetLastError();
 }
 
+// Wavefronts per item of demod_items_kernel: every wavefront takes at least
+// one antenna, and an item's antennas spread over fewer wavefronts (at least 8
+// per wavefront) while the grid still has many wavefronts per resident slot.
+int demod_waves_per_item(int A, int64_t items, int F) {
+  int wa = kWavesDemod;
+  while (wa > 1 && wa > A) wa /= 2;
+  while (wa > 1 && A / wa < 8 && items * (wa / 2) / F >= 8192) wa /= 2;
+  return wa;
+}
+
 template <int N, int QH, bool ZF>
 hipError_t demod_qh(const LaunchArgs& la, const float2* H, float2* xhat, uint8_t* bits) {
-  const int64_t grid = la.S * (la.T - 1);
-  constexpr int C = FftShape<N>::F == 1 ? RX_DEMOD_ILP : 1;
+  using Sh = FftShape<N>;
+  const int64_t items = la.S * (la.T - 1);
+  if constexpr (Sh::WPT == 1) {
+    const int wa = demod_waves_per_item(la.A, items, Sh::F);
+    if (Sh::F > 1 || wa < kWavesDemod) {
+      // several items per workgroup
+      const int ipw = (kWavesDemod / wa) * Sh::F;
+      const int64_t grid = (items + ipw - 1) / ipw;
+      size_t lds = fft_lds_bytes<N, kWavesDemod>();
+      const size_t red = (size_t)transforms_per_group<N, kWavesDemod>() * la.U * (sizeof(float2) + sizeof(float));
+      if (red > lds) lds = red;
+      hipError_t e = allow_lds(demod_items_kernel<N, QH, kWavesDemod, ZF>, lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((demod_items_kernel<N, QH, kWavesDemod, ZF>), dim3((unsigned)grid),
+                         dim3(64 * kWavesDemod), lds, la.stream, la.iq, la.S, la.A, la.T, la.CP, la.U, la.B, la.tw,
+                         H, xhat, bits, wa);
+      return hipGetLastError();
+    }
+  }
+  const int64_t grid = items;
+  constexpr int C = Sh::F == 1 ? RX_DEMOD_ILP : 1;
   size_t lds = fft_lds_bytes<N, kWavesDemod>() * C;
   const size_t red = (size_t)transforms_per_group<N, kWavesDemod>() * la.U * (sizeof(float2) + sizeof(float));
   if (red > lds) lds = red;

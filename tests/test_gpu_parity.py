@@ -247,3 +247,36 @@ def test_full_size_c4_launch_all_slots_checked(rx, fft_mode):
         check_H(as_complex(H[sl]), ref.H[src[sl]])
     check_xhat(as_complex(xhat), ref.xhat[src])
     check_bits(bits.cpu().numpy(), ref.bits[src], ref.xhat[src], cfg.bits_per_sym)
+
+
+# Antenna-count x FFT-length sweep points at their full size (about 1 GiB of
+# input each): launches with several (slot, symbol) items per workgroup and
+# one to four wavefronts per item, and the resident-grid estimate over short
+# transforms.  Eight distinct slots are tiled over the buffer; bits are checked
+# for every slot, H and x-hat for every slot of the first and last 64 and a
+# stride through the rest (the tail of the grid and its partial workgroup).
+@pytest.mark.parametrize("N,A", [(64, 1), (64, 2), (64, 3), (64, 16), (64, 128),
+                                 (1024, 1), (1024, 2), (1024, 8), (1024, 16), (1024, 32)])
+def test_sweep_point_full_size(rx, N, A):
+    from rxgen import sweep_config
+    if A in (1, 2, 8, 16, 32, 128):
+        cfg = sweep_config(N, A)
+    else:  # an antenna count off the sweep's powers of two, same input size
+        cfg = sweep_config(N, 2).replace(n_ant=A)
+        cfg = cfg.replace(n_slots=-(-(1 << 30) // cfg.slot_bytes))
+    S = cfg.n_slots
+    _say("sweep-point", cfg.name, "N", N, "A", A, "S", S, "seed", cfg.seed)
+    uniq = make_frames(cfg, n_slots=8)
+    ref = oracle.process_frame(uniq.iq, uniq.pilot, n_threads=8, **_kw(cfg))
+    plan = rx.Plan.from_config(cfg, uniq.pilot)
+    u = torch.from_numpy(uniq.iq).cuda()
+    iq = u[torch.arange(S, device="cuda") % 8].contiguous()
+    H, xhat, bits = plan.process(iq, want_H=True)
+    torch.cuda.synchronize()
+    src = np.arange(S) % 8
+    check_bits(bits.cpu().numpy(), ref.bits[src], ref.xhat[src], cfg.bits_per_sym)
+    pick = np.unique(np.concatenate([np.arange(min(64, S)), np.arange(max(0, S - 64), S),
+                                     np.arange(0, S, 97)]))
+    pk = torch.from_numpy(pick).cuda()
+    check_H(as_complex(H[pk]), ref.H[src[pick]])
+    check_xhat(as_complex(xhat[pk]), ref.xhat[src[pick]])

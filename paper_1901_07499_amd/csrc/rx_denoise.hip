@@ -323,7 +323,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     const float inv = s > 0.f ? 1.0f / s : 0.f;  // a zero row passes through (out = h)
     float ce = 0.f;                               // inference: energy of the correction s * a_4
 
-    for (int t0 = 0; t0 < U; t0 += TO) {
+    // the tile start is kept in a scalar register (readfirstlane): the loop
+    // holds barriers, and its exit must stay uniform even where the compiler
+    // computes the increment on divergent paths
+    for (int t0 = 0; t0 < U; t0 = __builtin_amdgcn_readfirstlane(t0 + TO)) {
       __syncthreads();  // the previous tile's readers are done
       for (int i = tid; i < NPOS; i += kBlock) {
         const int p = t0 - BASE_F + i;
@@ -396,9 +399,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
       }
       __syncthreads();
       // out[co][p] = b4[co] + sum_k P[(co, k)][p + k - 3]
-      for (int i = tid; i < TO; i += kBlock) {
+      const int nt = min(TO, U - t0);  // positions of this tile (a uniform bound: no early exit before
+                                       // the next tile's barrier)
+      for (int i = tid; i < nt; i += kBlock) {
         const int p = t0 + i;
-        if (p >= U) break;
         float o0 = b4[0], o1 = b4[1];
 #pragma unroll
         for (int k = 0; k < 7; k++) {
@@ -431,11 +435,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
       const bool fell = !__builtin_isfinite(E) || !(E <= io.fb_max2 * hs);
       if (fell) {
         for (int t0 = 0; t0 < U; t0 += TO)
-          for (int i = tid; i < TO; i += kBlock) {
-            const int p = t0 + i;
-            if (p >= U) break;
-            Hout[row * U + p] = hrow[p];
-          }
+          for (int i = tid; i < min(TO, U - t0); i += kBlock) Hout[row * U + t0 + i] = hrow[t0 + i];
       }
       if (tid == 0 && io.fell) io.fell[row] = fell ? 1 : 0;
     }

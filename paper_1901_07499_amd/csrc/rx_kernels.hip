@@ -290,6 +290,17 @@ __device__ __forceinline__ uint32_t qam_code(float2 x, int B) {
   return acc;
 }
 
+// x = z / g, the MRC output normalised by the channel energy (0 when g = 0),
+// as a reciprocal (within 1 ulp) and two products; a subnormal g takes the
+// division.
+__device__ __forceinline__ float2 mrc_equalize(float2 z, float g) {
+  if (g >= 1.17549435e-38f) {
+    const float r = __builtin_amdgcn_rcpf(g);
+    return make_float2(z.x * r, z.y * r);
+  }
+  return g > 0.f ? make_float2(z.x / g, z.y / g) : make_float2(0.f, 0.f);
+}
+
 // Output of subcarriers 4 qd .. 4 qd + 3 (fewer at the end of the row) of one
 // data symbol: sum(d, z, g) adds the partial sums of subcarrier d to z and g
 // (ZF: z is already the equalized symbol); x = z / g (0 when g = 0), then the
@@ -309,7 +320,7 @@ __device__ __forceinline__ void finish_quad(int qd, int U, int B, SumF sum, floa
     if constexpr (ZF) {
       x = zz;
     } else {
-      x = gg > 0.f ? make_float2(zz.x / gg, zz.y / gg) : make_float2(0.f, 0.f);
+      x = mrc_equalize(zz, gg);
     }
     if (xrow) xrow[d] = x;
     acc = (acc << B) | qam_code(x, B);
@@ -706,22 +717,39 @@ __global__ __launch_bounds__(64 * W) void demod_items_kernel(const uint32_t* __r
     }
   }
   __syncthreads();
-  const int nq = (U + 3) / 4;
-  const int row_bytes = U * B / 8;
-  for (int u = threadIdx.x; u < IPW * nq; u += 64 * W) {
-    const int litem = u / nq, qd = u - litem * nq;
-    const int64_t it = item0 + litem;
-    if (it >= items) break;  // items past the end lie at the end of u's range
+  // The workgroup's items are consecutive, so their x-hat rows and bit rows
+  // are contiguous: one thread per subcarrier (coalesced x-hat stores, the
+  // decision code to LDS), then one thread per output byte.
+  const int nitems = (int)min((int64_t)IPW, items - item0);  // the last workgroup may hold fewer
+  const int nsub = nitems * U;
+  uint8_t* codes = reinterpret_cast<uint8_t*>(rg + ROWS * U);  // [nsub]
+  for (int v = threadIdx.x; v < nsub; v += 64 * W) {
+    const int litem = v / U, d = v - litem * U;
     const int row0 = (litem / Sh::F) * Wa * Sh::F + litem % Sh::F;  // row of wavefront sub 0
-    finish_quad<ZF>(qd, U, B, [&](int d, float2& zz, float& gg) {
-      for (int k = 0; k < Wa; k++) {
-        const int r = row0 + k * Sh::F;
-        const float2 p = rz[r * U + d];
-        zz.x += p.x;
-        zz.y += p.y;
-        if constexpr (!ZF) gg += rg[r * U + d];
-      }
-    }, xhat ? xhat + it * U : nullptr, bits ? bits + it * row_bytes : nullptr);
+    float2 zz = make_float2(0.f, 0.f);
+    float gg = 0.f;
+    for (int k = 0; k < Wa; k++) {
+      const int r = row0 + k * Sh::F;
+      const float2 p = rz[r * U + d];
+      zz.x += p.x;
+      zz.y += p.y;
+      if constexpr (!ZF) gg += rg[r * U + d];
+    }
+    const float2 x = ZF ? zz : mrc_equalize(zz, gg);
+    if (xhat) xhat[item0 * U + v] = x;
+    codes[v] = (uint8_t)qam_code(x, B);
+  }
+  if (bits) {
+    __syncthreads();
+    const int nbytes = nsub * B / 8;  // every row is a whole number of bytes
+    uint8_t* out = bits + item0 * (int64_t)(U * B / 8);
+    for (int k = threadIdx.x; k < nbytes; k += 64 * W) {
+      // bits 8k .. 8k+7 of the concatenated codes (B bits each, MSB first)
+      const int b0 = 8 * k, c0 = b0 / B, c1 = (b0 + 7) / B;
+      uint32_t acc = 0;
+      for (int c = c0; c <= c1; c++) acc = (acc << B) | codes[c];
+      out[k] = (uint8_t)(acc >> ((c1 + 1) * B - b0 - 8));
+    }
   }
 }
 
@@ -978,7 +1006,8 @@ hipError_t demod_qh(const LaunchArgs& la, const float2* H, float2* xhat, uint8_t
       const int ipw = (kWavesDemod / wa) * Sh::F;
       const int64_t grid = (items + ipw - 1) / ipw;
       size_t lds = fft_lds_bytes<N, kWavesDemod>();
-      const size_t red = (size_t)transforms_per_group<N, kWavesDemod>() * la.U * (sizeof(float2) + sizeof(float));
+      // reduction rows (z, g) and one decision code per subcarrier
+      const size_t red = (size_t)transforms_per_group<N, kWavesDemod>() * la.U * (sizeof(float2) + sizeof(float) + 1);
       if (red > lds) lds = red;
       hipError_t e = allow_lds(demod_items_kernel<N, QH, kWavesDemod, ZF>, lds);
       if (e != hipSuccess) return e;

@@ -200,6 +200,37 @@ __global__ __launch_bounds__(64 * W) void estimate_kernel(const uint32_t* __rest
                          ps);
 }
 
+// Staged sample loads for transforms of at most 8 lanes (F >= 8 per
+// wavefront), where direct loads would give each load instruction L dwords of
+// each of F records: the records of a wavefront's job are read as 16-byte
+// pieces that cover them end to end (lane l, load q: dwords 4 (64 q + l) ..
+// + 3 of the F records laid end to end), then reordered.  The 16-byte pieces
+// of a wavefront's F records go to its LDS area, record f at dword f * kSt,
+// and each lane reads back its first-pass inputs x[li + r N / 16].  Ends
+// with the LDS area free again (wavefront-order fences around the reads).
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <int N>
+struct Staged {
+  using Sh = FftShape<N>;
+  static constexpr int kSt = N + Sh::L;             // dwords per record in LDS
+  static constexpr int kLoads = Sh::F * N / 256;    // 16-byte loads per lane (F N = 1024: 4)
+  static_assert(Sh::F * kSt <= 2 * Sh::F * Lds<N>::kSlot, "staging fits the exchange area");
+  static __device__ __forceinline__ void reorder(uint32_t (&raw)[Sh::P], const u32x4 (&w)[kLoads], uint32_t* stg,
+                                                 int f, int li) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q < kLoads; q++) {
+      const int e = 4 * (64 * q + lane), fq = e / N;
+      *reinterpret_cast<u32x4*>(stg + fq * kSt + (e - fq * N)) = w[q];
+    }
+    wave_fence();
+#pragma unroll
+    for (int r = 0; r < Sh::P; r++) raw[r] = stg[f * kSt + li + r * (N / 16)];
+    wave_fence();
+  }
+};
+
 // Uniform slots, transforms within one wavefront (N <= 1024): a grid of
 // resident workgroups only; transform slot g of the grid (G in all) takes jobs
 // g, g + G, ... of the S*A list of (slot, antenna) pilot symbols, the next
@@ -211,7 +242,7 @@ __global__ __launch_bounds__(64 * W) void estimate_kernel(const uint32_t* __rest
 // F slots of a wavefront hold consecutive jobs; the loop runs while the
 // wavefront's first job exists, and a slot past the end transforms the last
 // job's samples and stores nothing.
-template <int N, int W>
+template <int N, int W, bool STAGED>
 __global__ __launch_bounds__(64 * W) void estimate_grid_kernel(const uint32_t* __restrict__ iq, int64_t S, int A,
                                                                int T, int CP, int U, const float2* __restrict__ tw,
                                                                const float2* __restrict__ pf,
@@ -245,11 +276,55 @@ __global__ __launch_bounds__(64 * W) void estimate_grid_kernel(const uint32_t* _
     return iq + (ss * T * A + aa) * (int64_t)(N + CP) + CP;
   };
   float2* buf = lds + ts * Lds<N>::kSlot;
-  uint32_t nxt[Sh::P];
-  load_symbol<N>(nxt, rec(j, s, a), li, true);
+  // STAGED: this lane's 16-byte pieces belong to the jobs j0 + fq of the
+  // wavefront's slots fq, whose (slot, antenna) advance like the slot's own
+  using Sg = Staged<N>;
+  constexpr int NQ = STAGED ? Sg::kLoads : 1;
+  int64_t jq[NQ], sq[NQ];
+  int aq[NQ], nq[NQ];
+  if constexpr (STAGED) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q < NQ; q++) {
+      const int e = 4 * (64 * q + lane), fq = e / N;
+      nq[q] = e - fq * N;
+      jq[q] = j0 + fq;
+      sq[q] = jq[q] / A;
+      aq[q] = (int)(jq[q] - sq[q] * A);
+    }
+  }
+  uint32_t* stg = reinterpret_cast<uint32_t*>(lds + wave * Sh::F * Lds<N>::kSlot);
+  uint32_t nxt[STAGED ? 1 : Sh::P];
+  u32x4 nx4[NQ];
+  auto request = [&]() {
+    if constexpr (STAGED) {
+#pragma unroll
+      for (int q = 0; q < NQ; q++)
+        nx4[q] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(rec(jq[q], sq[q], aq[q]) + nq[q]));
+    } else {
+      load_symbol<N>(nxt, rec(j, s, a), li, true);
+    }
+  };
+  request();
   for (; j0 < jobs; j0 += G) {
     float2 v[Sh::P];
-    unpack_symbol<N>(v, nxt);
+    if constexpr (STAGED) {
+      uint32_t raw[Sh::P];
+      Sg::reorder(raw, nx4, stg, f, li);
+      unpack_symbol<N>(v, raw);
+#pragma unroll
+      for (int q = 0; q < NQ; q++) {
+        jq[q] += G;
+        sq[q] += Gs;
+        aq[q] += Ga;
+        if (aq[q] >= A) {
+          aq[q] -= A;
+          sq[q]++;
+        }
+      }
+    } else {
+      unpack_symbol<N>(v, nxt);
+    }
     const int64_t s0 = s, jcur = j;
     const int a0 = a;
     j += G;
@@ -259,7 +334,7 @@ __global__ __launch_bounds__(64 * W) void estimate_grid_kernel(const uint32_t* _
       a -= A;
       s++;
     }
-    if (j0 + G < jobs) load_symbol<N>(nxt, rec(j, s, a), li, true);
+    if (j0 + G < jobs) request();
     estimate_job<N>(v, el, buf, li, twr, jcur < jobs ? H + (s0 * A + a0) * (int64_t)U : nullptr, U, ps);
   }
 }
@@ -594,7 +669,7 @@ void demod_kernel(const uint32_t* __restrict__ iq, int64_t S, int A, int T, int 
 // a wavefront is one antenna of F items.  Each item's Wa partial sums meet in
 // LDS rows (row = transform slot, as in demod_tile); x-hat, decisions and
 // bits follow per item (paper Sec. II-C, MRC paragraph).
-template <int N, int QH, int W, bool ZF>
+template <int N, int QH, int W, bool ZF, bool STAGED>
 __global__ __launch_bounds__(64 * W) void demod_items_kernel(const uint32_t* __restrict__ iq, int64_t S, int A,
                                                              int T, int CP, int U, int B,
                                                              const float2* __restrict__ tw,
@@ -667,11 +742,48 @@ __global__ __launch_bounds__(64 * W) void demod_items_kernel(const uint32_t* __r
 
   float2* bufs[1] = {lds + ts * Lds<N>::kSlot};
   float2* const(&buf)[1] = bufs;
-  uint32_t nxt[Sh::P];
-  if (sub < A) load_symbol<N>(nxt, sym + (int64_t)sub * (N + CP), li, true);
+  // STAGED (transforms of at most 8 lanes): the F records of a job are read
+  // as 16-byte pieces that cover them end to end (lane l, load q: dwords
+  // 4 (64 q + l) .. + 3 of the F records laid end to end), then reordered
+  // through the wavefront's LDS area into the first pass's order (record f at
+  // dword f * kSt, kSt = N + L, so the strided reads hit distinct banks).
+  // Direct loads would give each instruction L dwords of each of F records.
+  using Sg = Staged<N>;
+  const uint32_t* srec[STAGED ? Sg::kLoads : 1];
+  if constexpr (STAGED) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q < Sg::kLoads; q++) {
+      const int e = 4 * (64 * q + lane), fq = e / N;
+      const int64_t iq_ = item0 + (wave / Wa) * Sh::F + fq;
+      const int64_t icq = iq_ < items ? iq_ : items - 1;
+      const int64_t sq = icq / Td;
+      const int tq = 1 + (int)(icq - sq * Td);
+      srec[q] = iq + (sq * T + tq) * (int64_t)A * (N + CP) + CP + (e - fq * N);
+    }
+  }
+  uint32_t* stg = reinterpret_cast<uint32_t*>(lds + wave * Sh::F * Lds<N>::kSlot);
+  uint32_t nxt[STAGED ? 1 : Sh::P];
+  u32x4 nx4[STAGED ? Sg::kLoads : 1];
+  auto request = [&](int aa) {
+    if constexpr (STAGED) {
+#pragma unroll
+      for (int q = 0; q < Sg::kLoads; q++)
+        nx4[q] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(srec[q] + (int64_t)aa * (N + CP)));
+    } else {
+      load_symbol<N>(nxt, sym + (int64_t)aa * (N + CP), li, true);
+    }
+  };
+  if (sub < A) request(sub);
   for (int a = sub; a < A; a += Wa) {  // uniform over the wavefront
     float2 v[1][Sh::P];
-    unpack_symbol<N>(v[0], nxt);
+    if constexpr (STAGED) {
+      uint32_t raw[Sh::P];
+      Sg::reorder(raw, nx4, stg, f, li);
+      unpack_symbol<N>(v[0], raw);
+    } else {
+      unpack_symbol<N>(v[0], nxt);
+    }
     fft_first_pass<N, 1>(v, buf, li);
     float2 hv[NI];
     if constexpr (Sh::F == 1) {
@@ -684,7 +796,7 @@ __global__ __launch_bounds__(64 * W) void demod_items_kernel(const uint32_t* __r
 #pragma unroll
       for (int i = 0; i < NI; i++) hv[i] = hrow[dcl(i)];
     }
-    if (a + Wa < A) load_symbol<N>(nxt, sym + (int64_t)(a + Wa) * (N + CP), li, true);
+    if (a + Wa < A) request(a + Wa);
     fft_rest<N, 1>(v, buf, li, twr);
 #pragma unroll
     for (int i = 0; i < NI; i++) {
@@ -933,34 +1045,43 @@ int resident_groups(K kernel, int block, size_t lds, int dev) {
   return cus * (per_cu > 0 ? per_cu : 1);
 }
 
-// Resident workgroups of estimate_grid_kernel<N, W> on the current device
+// Resident workgroups of estimate_grid_kernel<N, W, STAGED> on the current device
 // (0 on error), cached per device for this instantiation; concurrent first
 // calls store the same value.
-template <int N, int W>
+template <int N, int W, bool STAGED>
 int estimate_grid_capacity(size_t lds) {
   static int cached[64];
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 0;
   if (dev < 64 && cached[dev] > 0) return cached[dev];
-  const int n = resident_groups(estimate_grid_kernel<N, W>, 64 * W, lds, dev);
+  const int n = resident_groups(estimate_grid_kernel<N, W, STAGED>, 64 * W, lds, dev);
   if (dev < 64 && n > 0) cached[dev] = n;
   return n;
+}
+
+// The resident-grid estimate: only as many workgroups as the GPU holds at once.
+template <int N, bool STAGED>
+hipError_t estimate_grid_launch(const LaunchArgs& la, float2* H) {
+  const size_t lds = fft_lds_bytes<N, kWavesEst>();
+  hipError_t e = allow_lds(estimate_grid_kernel<N, kWavesEst, STAGED>, lds);
+  if (e != hipSuccess) return e;
+  const int resident = estimate_grid_capacity<N, kWavesEst, STAGED>(lds);
+  if (resident <= 0) return hipErrorInvalidValue;
+  constexpr int per_group = transforms_per_group<N, kWavesEst>();
+  const int64_t needed = (la.S * la.A + per_group - 1) / per_group;
+  const int64_t grid = needed < resident ? needed : resident;
+  hipLaunchKernelGGL((estimate_grid_kernel<N, kWavesEst, STAGED>), dim3((unsigned)grid), dim3(64 * kWavesEst), lds,
+                     la.stream, la.iq, la.S, la.A, la.T, la.CP, la.U, la.tw, la.pf, H, la.ps);
+  return hipGetLastError();
 }
 
 template <int N>
 hipError_t estimate_n(const LaunchArgs& la, float2* H) {
   if constexpr (FftShape<N>::WPT == 1) {
-    const size_t lds = fft_lds_bytes<N, kWavesEst>();
-    hipError_t e = allow_lds(estimate_grid_kernel<N, kWavesEst>, lds);
-    if (e != hipSuccess) return e;
-    const int resident = estimate_grid_capacity<N, kWavesEst>(lds);
-    if (resident <= 0) return hipErrorInvalidValue;
-    constexpr int per_group = transforms_per_group<N, kWavesEst>();
-    const int64_t needed = (la.S * la.A + per_group - 1) / per_group;
-    const int64_t grid = needed < resident ? needed : resident;
-    hipLaunchKernelGGL((estimate_grid_kernel<N, kWavesEst>), dim3((unsigned)grid), dim3(64 * kWavesEst), lds,
-                       la.stream, la.iq, la.S, la.A, la.T, la.CP, la.U, la.tw, la.pf, H, la.ps);
-    return hipGetLastError();
+    if constexpr (FftShape<N>::L <= 8) {
+      if (la.CP % 4 == 0 && reinterpret_cast<uintptr_t>(la.iq) % 16 == 0) return estimate_grid_launch<N, true>(la, H);
+    }
+    return estimate_grid_launch<N, false>(la, H);
   }
   const int per_block = transforms_per_group<N, kWavesEst>() * kJobsEst;  // antennas per workgroup
   const int bps = (la.A + per_block - 1) / per_block;
@@ -995,6 +1116,17 @@ int demod_waves_per_item(int A, int64_t items, int F) {
   return wa;
 }
 
+template <int N, int QH, bool ZF, bool STAGED>
+hipError_t demod_items_launch(const LaunchArgs& la, const float2* H, float2* xhat, uint8_t* bits, int wa,
+                              int64_t grid, size_t lds) {
+  hipError_t e = allow_lds(demod_items_kernel<N, QH, kWavesDemod, ZF, STAGED>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((demod_items_kernel<N, QH, kWavesDemod, ZF, STAGED>), dim3((unsigned)grid),
+                     dim3(64 * kWavesDemod), lds, la.stream, la.iq, la.S, la.A, la.T, la.CP, la.U, la.B, la.tw, H,
+                     xhat, bits, wa);
+  return hipGetLastError();
+}
+
 template <int N, int QH, bool ZF>
 hipError_t demod_qh(const LaunchArgs& la, const float2* H, float2* xhat, uint8_t* bits) {
   using Sh = FftShape<N>;
@@ -1009,12 +1141,13 @@ hipError_t demod_qh(const LaunchArgs& la, const float2* H, float2* xhat, uint8_t
       // reduction rows (z, g) and one decision code per subcarrier
       const size_t red = (size_t)transforms_per_group<N, kWavesDemod>() * la.U * (sizeof(float2) + sizeof(float) + 1);
       if (red > lds) lds = red;
-      hipError_t e = allow_lds(demod_items_kernel<N, QH, kWavesDemod, ZF>, lds);
-      if (e != hipSuccess) return e;
-      hipLaunchKernelGGL((demod_items_kernel<N, QH, kWavesDemod, ZF>), dim3((unsigned)grid),
-                         dim3(64 * kWavesDemod), lds, la.stream, la.iq, la.S, la.A, la.T, la.CP, la.U, la.B, la.tw,
-                         H, xhat, bits, wa);
-      return hipGetLastError();
+      // staged 16-byte sample loads for transforms of at most 8 lanes when
+      // every record piece is 16-byte aligned
+      if constexpr (Sh::L <= 8) {
+        if (la.CP % 4 == 0 && reinterpret_cast<uintptr_t>(la.iq) % 16 == 0)
+          return demod_items_launch<N, QH, ZF, true>(la, H, xhat, bits, wa, grid, lds);
+      }
+      return demod_items_launch<N, QH, ZF, false>(la, H, xhat, bits, wa, grid, lds);
     }
   }
   const int64_t grid = items;

@@ -94,6 +94,9 @@ CASES = {
     "N1024_U1000_wide": C2.replace(n_ant=6, n_used=1000, n_slots=2, n_sym=3),
     # 1600 of 2048 bins: the 2048-point demod's 8 + 8 register window
     "N2048_U1600_wide": C4.replace(n_ant=3, n_used=1600, n_slots=2, n_sym=3),
+    # 128-point transforms (8 lanes each) with a CP that keeps the records 16-byte aligned: the
+    # staged 16-byte sample loads (the CP 9 cases above take the direct loads)
+    "N128_CP8_staged": C2.replace(n_ant=6, fft_len=128, cp_len=8, n_used=72, bits_per_sym=4, n_slots=5, n_sym=7),
 }
 
 

@@ -81,43 +81,54 @@ constexpr int transforms_per_group() {
   return 64 * W / FftShape<N>::L;
 }
 
-// Per-lane constants of the estimate: the subcarrier of each spectrum
-// register (-1 when its bin is unused) and that subcarrier's pilot factor.
-template <int N>
+// Per-lane constants of the estimate for the spectrum registers that can hold
+// a used subcarrier: window register i holds spectrum register qof(i) (the
+// window of the demod kernel: q < QH and q >= P - QH; QH = P / 2 is the whole
+// spectrum), its subcarrier (-1 when its bin is unused) and that subcarrier's
+// pilot factor.
+template <int N, int QH = FftShape<N>::P / 2>
 struct EstLane {
-  int dq[FftShape<N>::P];
-  float2 pq[FftShape<N>::P];
+  static constexpr int NI = 2 * QH;
+  static_assert(NI <= FftShape<N>::P, "window wider than the lane's spectrum");
+  static constexpr int qof(int i) { return i < QH ? i : FftShape<N>::P - NI + i; }
+  int dq[NI];
+  float2 pq[NI];
   __device__ __forceinline__ void init(int li, int U, const float2* __restrict__ pf) {
 #pragma unroll
-    for (int q = 0; q < FftShape<N>::P; q++) {
-      dq[q] = sub_of_bin(li + FftShape<N>::L * q, N, U);
-      pq[q] = pf[dq[q] >= 0 ? dq[q] : 0];  // clamped load; unused bins are never stored
+    for (int i = 0; i < NI; i++) {
+      dq[i] = sub_of_bin(li + FftShape<N>::L * qof(i), N, U);
+      pq[i] = pf[dq[i] >= 0 ? dq[i] : 0];  // clamped load; unused bins are never stored
     }
   }
 };
 
 // One pilot symbol (samples unpacked into v): FFT, LS by the pilot factors,
-// H row out (hrow null: nothing stored).  With a comb pilot (every ps-th used
-// subcarrier) the LS values go to the transform's LDS slot and every
-// subcarrier is interpolated from them.  Ends with an exchange fence.
-template <int N, int S, bool LL>
-__device__ __forceinline__ void estimate_job(float2 (&v)[FftShape<N>::P], const EstLane<N>& el, float2* buf, int li,
-                                             const FftTwiddles<N, S, LL>& twr, float2* __restrict__ hrow, int U, int ps) {
+// H row out (hrow null: nothing stored).  COMB: a comb pilot (every ps-th
+// used subcarrier): the LS values go to the transform's LDS slot and every
+// subcarrier is interpolated from them.  Only the window's spectrum registers
+// are used, so the last pass computes nothing else.  Ends with an exchange
+// fence.
+template <int N, int S, bool LL, int QH, bool COMB>
+__device__ __forceinline__ void estimate_job(float2 (&v)[FftShape<N>::P], const EstLane<N, QH>& el, float2* buf,
+                                             int li, const FftTwiddles<N, S, LL>& twr, float2* __restrict__ hrow,
+                                             int U, int ps) {
   using Sh = FftShape<N>;
+  using El = EstLane<N, QH>;
   fft_in_regs<N>(v, buf, li, twr);
-  if (ps <= 1) {
+  if constexpr (!COMB) {
     if (hrow) {
 #pragma unroll
-      for (int q = 0; q < Sh::P; q++)
-        if (el.dq[q] >= 0) hrow[el.dq[q]] = cmul(v[Spectrum<N, S>::reg(q)], el.pq[q]);
+      for (int i = 0; i < El::NI; i++)
+        if (el.dq[i] >= 0) hrow[el.dq[i]] = cmul(v[Spectrum<N, S>::reg(El::qof(i))], el.pq[i]);
     }
   } else {
     // comb: LS on the pilot subcarriers into this transform's LDS slot (the
     // FFT's last LDS reads are behind), then every subcarrier
     exchange_fence<N>();
 #pragma unroll
-    for (int q = 0; q < Sh::P; q++)
-      if (el.dq[q] >= 0 && el.dq[q] % ps == 0) buf[el.dq[q] / ps] = cmul(v[Spectrum<N, S>::reg(q)], el.pq[q]);
+    for (int i = 0; i < El::NI; i++)
+      if (el.dq[i] >= 0 && el.dq[i] % ps == 0)
+        buf[el.dq[i] / ps] = cmul(v[Spectrum<N, S>::reg(El::qof(i))], el.pq[i]);
     exchange_fence<N>();
     if (hrow)
       for (int d = li; d < U; d += Sh::L) hrow[d] = comb_value(buf, d, U, ps);
@@ -132,7 +143,7 @@ __device__ __forceinline__ void estimate_job(float2 (&v)[FftShape<N>::P], const 
 // uniform over whoever shares an exchange fence (the wavefront, or the
 // workgroup for two-wavefront transforms): a transform whose antenna is past
 // A transforms a valid antenna's samples and stores nothing.
-template <int N, int W, int J, int S, bool LL>
+template <int N, int W, int J, int QH, bool COMB, int S, bool LL>
 __device__ __forceinline__ void estimate_tile(const uint32_t* __restrict__ slot_iq, int A, int CP, int U,
                                               const float2* __restrict__ pf, float2* __restrict__ Hs,
                                               int a_wg, float2* lds, const FftTwiddles<N, S, LL>& twr, int ps) {
@@ -144,7 +155,7 @@ __device__ __forceinline__ void estimate_tile(const uint32_t* __restrict__ slot_
   // workgroup's first when a transform spans wavefronts
   const int a_lead = Sh::WPT > 1 ? a_wg : a_wg + ts - f;
   if (a_lead >= A) return;
-  EstLane<N> el;
+  EstLane<N, QH> el;
   el.init(li, U, pf);
   const uint32_t* pilot_sym = slot_iq + CP;  // symbol 0
   // record of antenna a, or of the (valid) lead antenna lead when a >= A
@@ -160,7 +171,7 @@ __device__ __forceinline__ void estimate_tile(const uint32_t* __restrict__ slot_
     float2 v[Sh::P];
     unpack_symbol<N>(v, nxt);
     if (j + 1 < J && lead + TPW < A) load_symbol<N>(nxt, rec_of(a + TPW, lead + TPW), li, a + TPW < A);
-    estimate_job<N>(v, el, buf, li, twr, a < A ? Hs + (int64_t)a * U : nullptr, U, ps);
+    estimate_job<N, S, LL, QH, COMB>(v, el, buf, li, twr, a < A ? Hs + (int64_t)a * U : nullptr, U, ps);
   }
 }
 
@@ -183,8 +194,15 @@ __device__ __forceinline__ void tile_setup(FftTwiddles<N, S, LL>& twr, float2* t
 template <int N>
 constexpr bool estimate_twiddles_in_lds() { return N < 1024; }
 
-template <int N, int W, int J>
-__global__ __launch_bounds__(64 * W) void estimate_kernel(const uint32_t* __restrict__ iq, int A, int T, int CP,
+// The N = 2048 estimate with the 5-register window needs a register budget
+// of 3 wavefronts per SIMD to stay there (the compiler otherwise takes 170
+// VGPRs and drops to 2).
+template <int N, int QH, bool COMB>
+constexpr int estimate_min_waves() { return N == 2048 && QH <= 5 && !COMB ? 3 : 1; }
+
+template <int N, int W, int J, int QH, bool COMB>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(estimate_min_waves<N, QH, COMB>())))
+void estimate_kernel(const uint32_t* __restrict__ iq, int A, int T, int CP,
                                                           int U, const float2* __restrict__ tw,
                                                           const float2* __restrict__ pf, float2* __restrict__ H,
                                                           int blocks_per_slot, int ps) {
@@ -196,8 +214,8 @@ __global__ __launch_bounds__(64 * W) void estimate_kernel(const uint32_t* __rest
   const int64_t s = blockIdx.x / blocks_per_slot;
   const int blk = blockIdx.x % blocks_per_slot;
   const int a_wg = blk * (transforms_per_group<N, W>() * J);
-  estimate_tile<N, W, J>(iq + s * T * (int64_t)A * (N + CP), A, CP, U, pf, H + s * A * (int64_t)U, a_wg, lds, twr,
-                         ps);
+  estimate_tile<N, W, J, QH, COMB>(iq + s * T * (int64_t)A * (N + CP), A, CP, U, pf, H + s * A * (int64_t)U, a_wg,
+                                   lds, twr, ps);
 }
 
 // Staged sample loads for transforms of at most 8 lanes (F >= 8 per
@@ -242,7 +260,7 @@ struct Staged {
 // F slots of a wavefront hold consecutive jobs; the loop runs while the
 // wavefront's first job exists, and a slot past the end transforms the last
 // job's samples and stores nothing.
-template <int N, int W, bool STAGED>
+template <int N, int W, bool STAGED, int QH, bool COMB>
 __global__ __launch_bounds__(64 * W) void estimate_grid_kernel(const uint32_t* __restrict__ iq, int64_t S, int A,
                                                                int T, int CP, int U, const float2* __restrict__ tw,
                                                                const float2* __restrict__ pf,
@@ -260,7 +278,7 @@ __global__ __launch_bounds__(64 * W) void estimate_grid_kernel(const uint32_t* _
   const int64_t G = (int64_t)gridDim.x * W * Sh::F;
   int64_t j0 = ((int64_t)blockIdx.x * W + wave) * Sh::F;  // the wavefront's first job (uniform)
   if (j0 >= jobs) return;                                 // no workgroup barrier below
-  EstLane<N> el;
+  EstLane<N, QH> el;
   el.init(li, U, pf);
   // (slot, antenna) of this slot's job j, advanced by G per step without a
   // division (meaningless once j is past the list: the last job is read)
@@ -335,7 +353,8 @@ __global__ __launch_bounds__(64 * W) void estimate_grid_kernel(const uint32_t* _
       s++;
     }
     if (j0 + G < jobs) request();
-    estimate_job<N>(v, el, buf, li, twr, jcur < jobs ? H + (s0 * A + a0) * (int64_t)U : nullptr, U, ps);
+    estimate_job<N, 0, true, QH, COMB>(v, el, buf, li, twr, jcur < jobs ? H + (s0 * A + a0) * (int64_t)U : nullptr,
+                                       U, ps);
   }
 }
 
@@ -911,7 +930,8 @@ __global__ __launch_bounds__(64 * W) void batch_estimate_kernel(const FrameDesc*
     if (tile >= n_tiles) break;
     const FrameDesc d = fd[frame];
     const int a_wg = (tile - d.est_tile0) * (transforms_per_group<N, W>() * J);
-    estimate_tile<N, W, J>(io.iq + d.iq_off, d.A, d.CP, d.U, d.pf, io.H + d.h_off, a_wg, lds, twr, 1);
+    estimate_tile<N, W, J, FftShape<N>::P / 2, false>(io.iq + d.iq_off, d.A, d.CP, d.U, d.pf, io.H + d.h_off, a_wg,
+                                                     lds, twr, 1);
   }
 }
 
@@ -1045,53 +1065,70 @@ int resident_groups(K kernel, int block, size_t lds, int dev) {
   return cus * (per_cu > 0 ? per_cu : 1);
 }
 
-// Resident workgroups of estimate_grid_kernel<N, W, STAGED> on the current device
-// (0 on error), cached per device for this instantiation; concurrent first
-// calls store the same value.
-template <int N, int W, bool STAGED>
+// Resident workgroups of an estimate_grid_kernel instantiation on the current
+// device (0 on error), cached per device for this instantiation; concurrent
+// first calls store the same value.
+template <int N, int W, bool STAGED, int QH, bool COMB>
 int estimate_grid_capacity(size_t lds) {
   static int cached[64];
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 0;
   if (dev < 64 && cached[dev] > 0) return cached[dev];
-  const int n = resident_groups(estimate_grid_kernel<N, W, STAGED>, 64 * W, lds, dev);
+  const int n = resident_groups(estimate_grid_kernel<N, W, STAGED, QH, COMB>, 64 * W, lds, dev);
   if (dev < 64 && n > 0) cached[dev] = n;
   return n;
 }
 
 // The resident-grid estimate: only as many workgroups as the GPU holds at once.
-template <int N, bool STAGED>
+template <int N, bool STAGED, int QH, bool COMB>
 hipError_t estimate_grid_launch(const LaunchArgs& la, float2* H) {
   const size_t lds = fft_lds_bytes<N, kWavesEst>();
-  hipError_t e = allow_lds(estimate_grid_kernel<N, kWavesEst, STAGED>, lds);
+  hipError_t e = allow_lds(estimate_grid_kernel<N, kWavesEst, STAGED, QH, COMB>, lds);
   if (e != hipSuccess) return e;
-  const int resident = estimate_grid_capacity<N, kWavesEst, STAGED>(lds);
+  const int resident = estimate_grid_capacity<N, kWavesEst, STAGED, QH, COMB>(lds);
   if (resident <= 0) return hipErrorInvalidValue;
   constexpr int per_group = transforms_per_group<N, kWavesEst>();
   const int64_t needed = (la.S * la.A + per_group - 1) / per_group;
   const int64_t grid = needed < resident ? needed : resident;
-  hipLaunchKernelGGL((estimate_grid_kernel<N, kWavesEst, STAGED>), dim3((unsigned)grid), dim3(64 * kWavesEst), lds,
-                     la.stream, la.iq, la.S, la.A, la.T, la.CP, la.U, la.tw, la.pf, H, la.ps);
+  hipLaunchKernelGGL((estimate_grid_kernel<N, kWavesEst, STAGED, QH, COMB>), dim3((unsigned)grid),
+                     dim3(64 * kWavesEst), lds, la.stream, la.iq, la.S, la.A, la.T, la.CP, la.U, la.tw, la.pf, H,
+                     la.ps);
   return hipGetLastError();
 }
 
-template <int N>
-hipError_t estimate_n(const LaunchArgs& la, float2* H) {
+template <int N, int QH, bool COMB>
+hipError_t estimate_nq(const LaunchArgs& la, float2* H) {
   if constexpr (FftShape<N>::WPT == 1) {
     if constexpr (FftShape<N>::L <= 8) {
-      if (la.CP % 4 == 0 && reinterpret_cast<uintptr_t>(la.iq) % 16 == 0) return estimate_grid_launch<N, true>(la, H);
+      if (la.CP % 4 == 0 && reinterpret_cast<uintptr_t>(la.iq) % 16 == 0)
+        return estimate_grid_launch<N, true, QH, COMB>(la, H);
     }
-    return estimate_grid_launch<N, false>(la, H);
+    return estimate_grid_launch<N, false, QH, COMB>(la, H);
   }
   const int per_block = transforms_per_group<N, kWavesEst>() * kJobsEst;  // antennas per workgroup
   const int bps = (la.A + per_block - 1) / per_block;
   const int64_t grid = la.S * bps;
   const size_t lds = fft_lds_bytes<N, kWavesEst>();
-  hipError_t e = allow_lds(estimate_kernel<N, kWavesEst, kJobsEst>, lds);
+  hipError_t e = allow_lds(estimate_kernel<N, kWavesEst, kJobsEst, QH, COMB>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((estimate_kernel<N, kWavesEst, kJobsEst>), dim3((unsigned)grid), dim3(64 * kWavesEst), lds,
-                     la.stream, la.iq, la.A, la.T, la.CP, la.U, la.tw, la.pf, H, bps, la.ps);
+  hipLaunchKernelGGL((estimate_kernel<N, kWavesEst, kJobsEst, QH, COMB>), dim3((unsigned)grid),
+                     dim3(64 * kWavesEst), lds, la.stream, la.iq, la.A, la.T, la.CP, la.U, la.tw, la.pf, H, bps,
+                     la.ps);
   return hipGetLastError();
+}
+
+// The estimate with the demod's register-window tiers for a block pilot (the
+// last pass computes only the used window) and the whole spectrum for a comb.
+template <int N>
+hipError_t estimate_n(const LaunchArgs& la, float2* H) {
+  constexpr int L = FftShape<N>::L;
+  if (la.ps > 1) return estimate_nq<N, 8, true>(la, H);
+  const int need = (la.U / 2 + 1 + L - 1) / L;
+  if (need <= 2) return estimate_nq<N, 2, false>(la, H);
+  if (need <= 4) return estimate_nq<N, 4, false>(la, H);
+  if (need <= 5) return estimate_nq<N, 5, false>(la, H);
+  if (need <= 8) return estimate_nq<N, 8, false>(la, H);
+  return hipErrorInvalidValue;
 }
 
 template <int N>

@@ -688,8 +688,14 @@ void demod_kernel(const uint32_t* __restrict__ iq, int64_t S, int A, int T, int 
 // a wavefront is one antenna of F items.  Each item's Wa partial sums meet in
 // LDS rows (row = transform slot, as in demod_tile); x-hat, decisions and
 // bits follow per item (paper Sec. II-C, MRC paragraph).
+// The N = 1024 items kernel with the 5-register window is held at 3
+// wavefronts per SIMD (168 VGPRs; the compiler would otherwise take 169).
+template <int N, int QH>
+constexpr int demod_items_min_waves() { return N == 1024 && QH == 5 ? 3 : 1; }
+
 template <int N, int QH, int W, bool ZF, bool STAGED>
-__global__ __launch_bounds__(64 * W) void demod_items_kernel(const uint32_t* __restrict__ iq, int64_t S, int A,
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(demod_items_min_waves<N, QH>())))
+void demod_items_kernel(const uint32_t* __restrict__ iq, int64_t S, int A,
                                                              int T, int CP, int U, int B,
                                                              const float2* __restrict__ tw,
                                                              const float2* __restrict__ H,
@@ -834,52 +840,80 @@ __global__ __launch_bounds__(64 * W) void demod_items_kernel(const uint32_t* __r
     exchange_fence<N>();  // this job's LDS reads precede the next job's writes
   }
 
-  // Partial sums of every transform slot to its LDS row, then per item the
-  // sum over its Wa rows in a fixed order.
+  // The workgroup's items are consecutive, so their x-hat rows and bit rows
+  // are contiguous.  x-hat and the decision codes (to LDS) come straight from
+  // the registers when one wavefront holds an item (Wa == 1); otherwise every
+  // transform slot's partial sums go to its LDS row and one thread per
+  // subcarrier sums the item's Wa rows in a fixed order.  Then one thread per
+  // four codes packs the bits.
   constexpr int ROWS = W * Sh::F;
+  const int nitems = (int)min((int64_t)IPW, items - item0);  // the last workgroup may hold fewer
+  const int nsub = nitems * U;
   __syncthreads();
   float2* rz = lds;                                      // [ROWS][U]
   float* rg = reinterpret_cast<float*>(lds + ROWS * U);  // [ROWS][U]
+  uint8_t* codes = reinterpret_cast<uint8_t*>(rg + ROWS * U);  // [nsub] (+ 4 bytes of slack)
+  if (Wa == 1) {
+    const int litem = wave * Sh::F + f;
+    if (litem < nitems) {
 #pragma unroll
-  for (int i = 0; i < NI; i++) {
-    if (wok(i)) {
-      rz[ts * U + li + doff(i)] = z[i];
-      if constexpr (!ZF) rg[ts * U + li + doff(i)] = g[i];
+      for (int i = 0; i < NI; i++) {
+        if (wok(i)) {
+          const int d = li + doff(i);
+          const float2 x = ZF ? z[i] : mrc_equalize(z[i], g[i]);
+          if (xhat) xhat[(item0 + litem) * U + d] = x;
+          codes[litem * U + d] = (uint8_t)qam_code(x, B);
+        }
+      }
     }
-  }
-  __syncthreads();
-  // The workgroup's items are consecutive, so their x-hat rows and bit rows
-  // are contiguous: one thread per subcarrier (coalesced x-hat stores, the
-  // decision code to LDS), then one thread per output byte.
-  const int nitems = (int)min((int64_t)IPW, items - item0);  // the last workgroup may hold fewer
-  const int nsub = nitems * U;
-  uint8_t* codes = reinterpret_cast<uint8_t*>(rg + ROWS * U);  // [nsub]
-  for (int v = threadIdx.x; v < nsub; v += 64 * W) {
-    const int litem = v / U, d = v - litem * U;
-    const int row0 = (litem / Sh::F) * Wa * Sh::F + litem % Sh::F;  // row of wavefront sub 0
-    float2 zz = make_float2(0.f, 0.f);
-    float gg = 0.f;
-    for (int k = 0; k < Wa; k++) {
-      const int r = row0 + k * Sh::F;
-      const float2 p = rz[r * U + d];
-      zz.x += p.x;
-      zz.y += p.y;
-      if constexpr (!ZF) gg += rg[r * U + d];
+  } else {
+#pragma unroll
+    for (int i = 0; i < NI; i++) {
+      if (wok(i)) {
+        rz[ts * U + li + doff(i)] = z[i];
+        if constexpr (!ZF) rg[ts * U + li + doff(i)] = g[i];
+      }
     }
-    const float2 x = ZF ? zz : mrc_equalize(zz, gg);
-    if (xhat) xhat[item0 * U + v] = x;
-    codes[v] = (uint8_t)qam_code(x, B);
+    __syncthreads();
+    // subcarrier v = litem * U + d, stepped without a division
+    constexpr int kStride = 64 * W;
+    const int sq = kStride / U, sr = kStride - sq * U;
+    int litem = threadIdx.x / U, d = threadIdx.x - litem * U;
+    for (int v = threadIdx.x; v < nsub; v += kStride) {
+      const int row0 = (litem / Sh::F) * Wa * Sh::F + litem % Sh::F;  // row of wavefront sub 0
+      float2 zz = make_float2(0.f, 0.f);
+      float gg = 0.f;
+      for (int k = 0; k < Wa; k++) {
+        const int r = row0 + k * Sh::F;
+        const float2 p = rz[r * U + d];
+        zz.x += p.x;
+        zz.y += p.y;
+        if constexpr (!ZF) gg += rg[r * U + d];
+      }
+      const float2 x = ZF ? zz : mrc_equalize(zz, gg);
+      if (xhat) xhat[item0 * U + v] = x;
+      codes[v] = (uint8_t)qam_code(x, B);
+      d += sr;
+      litem += sq;
+      if (d >= U) {
+        d -= U;
+        litem++;
+      }
+    }
   }
   if (bits) {
     __syncthreads();
-    const int nbytes = nsub * B / 8;  // every row is a whole number of bytes
+    // codes 4k .. 4k+3 (fewer at the end) -> bytes k B / 2 .. of the bit rows
+    // (every row is a whole number of bytes, so the rows concatenate)
     uint8_t* out = bits + item0 * (int64_t)(U * B / 8);
-    for (int k = threadIdx.x; k < nbytes; k += 64 * W) {
-      // bits 8k .. 8k+7 of the concatenated codes (B bits each, MSB first)
-      const int b0 = 8 * k, c0 = b0 / B, c1 = (b0 + 7) / B;
+    for (int k = threadIdx.x; 4 * k < nsub; k += 64 * W) {
+      const int n = min(4, nsub - 4 * k);
+      const uint32_t w = *reinterpret_cast<const uint32_t*>(codes + 4 * k);
       uint32_t acc = 0;
-      for (int c = c0; c <= c1; c++) acc = (acc << B) | codes[c];
-      out[k] = (uint8_t)(acc >> ((c1 + 1) * B - b0 - 8));
+      for (int e = 0; e < n; e++) acc = (acc << B) | ((w >> (8 * e)) & 0xffu);
+      const int nbytes = n * B / 8;
+      for (int byte = 0; byte < nbytes; byte++)
+        out[k * (B / 2) + byte] = (uint8_t)(acc >> (n * B - 8 * (byte + 1)));
     }
   }
 }
@@ -1175,8 +1209,10 @@ hipError_t demod_qh(const LaunchArgs& la, const float2* H, float2* xhat, uint8_t
       const int ipw = (kWavesDemod / wa) * Sh::F;
       const int64_t grid = (items + ipw - 1) / ipw;
       size_t lds = fft_lds_bytes<N, kWavesDemod>();
-      // reduction rows (z, g) and one decision code per subcarrier
-      const size_t red = (size_t)transforms_per_group<N, kWavesDemod>() * la.U * (sizeof(float2) + sizeof(float) + 1);
+      // reduction rows (z, g) and one decision code per subcarrier, with 4
+      // bytes of slack for the packing's last 4-byte read
+      const size_t red =
+          (size_t)transforms_per_group<N, kWavesDemod>() * la.U * (sizeof(float2) + sizeof(float) + 1) + 4;
       if (red > lds) lds = red;
       // staged 16-byte sample loads for transforms of at most 8 lanes when
       // every record piece is 16-byte aligned

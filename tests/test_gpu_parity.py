@@ -97,6 +97,9 @@ CASES = {
     # 128-point transforms (8 lanes each) with a CP that keeps the records 16-byte aligned: the
     # staged 16-byte sample loads (the CP 9 cases above take the direct loads)
     "N128_CP8_staged": C2.replace(n_ant=6, fft_len=128, cp_len=8, n_used=72, bits_per_sym=4, n_slots=5, n_sym=7),
+    # two and three antennas at N = 1024: two wavefronts per item, several items per workgroup
+    "A2_two_waves_per_item": C2.replace(n_ant=2, n_slots=3, n_sym=5),
+    "A3_two_waves_per_item": C2.replace(n_ant=3, n_slots=2, n_sym=6),
 }
 
 
@@ -260,7 +263,7 @@ def test_full_size_c4_launch_all_slots_checked(rx, fft_mode):
 # stride through the rest (the tail of the grid and its partial workgroup).
 @pytest.mark.parametrize("N,A", [(64, 1), (64, 2), (64, 3), (64, 16), (64, 128),
                                  (1024, 1), (1024, 2), (1024, 8), (1024, 16), (1024, 32)])
-def test_sweep_point_full_size(rx, N, A):
+def test_sweep_point_full_size(rx, N, A, combiner=0):
     from rxgen import sweep_config
     if A in (1, 2, 8, 16, 32, 128):
         cfg = sweep_config(N, A)
@@ -270,8 +273,8 @@ def test_sweep_point_full_size(rx, N, A):
     S = cfg.n_slots
     _say("sweep-point", cfg.name, "N", N, "A", A, "S", S, "seed", cfg.seed)
     uniq = make_frames(cfg, n_slots=8)
-    ref = oracle.process_frame(uniq.iq, uniq.pilot, n_threads=8, **_kw(cfg))
-    plan = rx.Plan.from_config(cfg, uniq.pilot)
+    ref = oracle.process_frame(uniq.iq, uniq.pilot, n_threads=8, combiner=combiner, **_kw(cfg))
+    plan = rx.Plan.from_config(cfg, uniq.pilot, combiner)
     u = torch.from_numpy(uniq.iq).cuda()
     iq = u[torch.arange(S, device="cuda") % 8].contiguous()
     H, xhat, bits = plan.process(iq, want_H=True)
@@ -283,3 +286,10 @@ def test_sweep_point_full_size(rx, N, A):
     pk = torch.from_numpy(pick).cuda()
     check_H(as_complex(H[pk]), ref.H[src[pick]])
     check_xhat(as_complex(xhat[pk]), ref.xhat[src[pick]])
+
+
+# ZF on sweep-sized launches: one wavefront per item holding eight antennas (N = 1024, A = 8) and
+# the 16-transform wavefronts at N = 64 with two wavefronts per item (A = 16)
+@pytest.mark.parametrize("N,A", [(1024, 8), (64, 16)])
+def test_sweep_point_full_size_zf(rx, N, A):
+    test_sweep_point_full_size(rx, N, A, combiner=1)

@@ -171,6 +171,56 @@ def test_bf16_rounding_matches_torch():
     assert dn.bf16(np.array([1 + 3 * 2 ** -8]))[0] == 1 + 2 ** -6
 
 
+def _tbf16(x):
+    """bf16 rounding by torch's conversion (an implementation other than the oracle's)."""
+    f = torch.from_numpy(np.asarray(x, dtype=np.float64).astype(np.float32))
+    return f.to(torch.bfloat16).to(torch.float64).numpy()
+
+
+def test_bf16_rounding_points_closed_form():
+    # A sparse network whose weights and inputs lie off the bf16 grid, so that
+    # each rounding point of the bf16 mode -- the normalised input, every
+    # weight, every ReLU output and the output deltas -- changes the result.
+    # The forward output and the last layer's bias gradient must equal a
+    # hand-built evaluation exactly (products of bf16 values and sums of a few
+    # of them are exact in FP64, so no summation order enters).
+    U = 8
+    layers = [(np.zeros((co, ci, dn.TAPS)), np.zeros(co)) for ci, co in dn.LAYERS]
+    w1, w2, w3 = 1 + 3 * 2.0 ** -9, 1.5 + 3 * 2.0 ** -10, 0.75 + 5 * 2.0 ** -12
+    w4, w5 = 0.5 + 3 * 2.0 ** -11, -0.25 - 5 * 2.0 ** -13
+    layers[0][0][0, 0, 2:5] = w1  # a1[0][p] = w1 (x[p-1] + x[p] + x[p+1]) over the real input channel
+    layers[1][0][0, 0, 3] = w2
+    layers[2][0][0, 0, 3] = w3
+    layers[3][0][0, 0, 3] = w4    # real output
+    layers[3][0][1, 0, 3] = w5    # imaginary output
+    theta = dn.pack(layers)
+    rng = np.random.default_rng(5)
+    sign = np.array([[1, 1, -1, 1, 1, -1, -1, 1]], dtype=np.float64)
+    h = sign * (1 + rng.integers(1, 200, size=(1, U)) * 2.0 ** -11) + 1j * rng.standard_normal((1, U))
+    ht = h + 0.25 * (rng.standard_normal((1, U)) + 1j * rng.standard_normal((1, U)))
+
+    s = np.sqrt(np.mean(np.abs(h) ** 2))
+    x = _tbf16(h.real[0] / s)
+    xp = np.concatenate([[0.0], x, [0.0]])
+    a1 = _tbf16(w1) * (xp[:-2] + xp[1:-1] + xp[2:])
+    x1 = _tbf16(np.maximum(a1, 0.0))
+    x2 = _tbf16(np.maximum(_tbf16(w2) * x1, 0.0))
+    x3 = _tbf16(np.maximum(_tbf16(w3) * x2, 0.0))
+    a4r, a4i = _tbf16(w4) * x3, _tbf16(w5) * x3
+    assert (a1 > 0).any() and (a1 < 0).any()  # the ReLU both passes and blocks
+    want = h + s * (a4r + 1j * a4i)
+    got = dn.forward(theta, h, bf16_ops=True)
+    assert np.array_equal(got, want)
+    assert not np.allclose(dn.forward(theta, h), want, rtol=1e-9, atol=0)  # the roundings matter
+
+    n = U
+    er = h.real[0] / s + a4r - ht.real[0] / s
+    ei = h.imag[0] / s + a4i - ht.imag[0] / s
+    gb4 = np.array([_tbf16(2 * er / n).sum(), _tbf16(2 * ei / n).sum()])
+    _, g = dn.loss_grad(theta, h, ht, bf16_ops=True)
+    assert np.array_equal(g[-2:], gb4)
+
+
 def test_bf16_operands_stay_within_their_error_bound():
     # Each rounding is within 2^-9 relative; over 4 layers the refined part of
     # the output must stay within a few percent of the exact one, and the

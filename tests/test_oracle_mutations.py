@@ -116,6 +116,10 @@ DN_MUTANTS = {
     "fallback_limit_not_squared": ("~(e <= max_corr ** 2 * np.sum", "~(e <= max_corr * np.sum"),
     "fallback_ignores_non_finite": ("fell = ~np.isfinite(e) | ~(e", "fell = ~(e"),
     "bf16_truncates": ("(u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000", "u & 0xFFFF0000"),
+    "bf16_input_not_rounded": ("x = rnd(_input(h, s))", "x = _input(h, s)"),
+    "bf16_weights_not_rounded": ("a = conv(x, rnd(W), b)", "a = conv(x, W, b)"),
+    "bf16_activation_not_rounded": ("x = rnd(np.maximum(a, 0.0))", "x = np.maximum(a, 0.0)"),
+    "bf16_delta_not_rounded": ("delta = rnd(2.0 * e / n)", "delta = 2.0 * e / n"),
     "term_rss_not_squared": ("np.einsum(\"rou,rcu->oc\", delta ** 2, xp[:, :, k:k + U] ** 2)",
                              "np.einsum(\"rou,rcu->oc\", delta ** 2, xp[:, :, k:k + U])"),
     "term_rss_tap_shifted": ("delta ** 2, xp[:, :, k:k + U] ** 2", "delta ** 2, xp[:, :, 2 * HALF - k:2 * HALF - k + U] ** 2"),

@@ -10,8 +10,11 @@ JSON line.  Defaults: the 64-antenna, N=1024, 200-slot workload, 1 GPU.
 
 Timing: W untimed steps, then untimed steps until the clocks have settled
 (windows of 20 steps, at least 200 ms, two windows within 2 %; reported as
-warmup_ms / warmup_settle_steps), then exactly K timed steps with an event
-after each (ms_per_step over all K, step_ms_median and step_ms_min).
+warmup_ms / warmup_settle_steps), a synchronisation, about 15 ms of untimed
+steps enqueued behind it (lead_in_steps: the GPU idles at the
+synchronisation and its clocks need that long to come back), then exactly K
+timed steps with an event before each and one after the last (ms_per_step
+over all K, step_ms_median and step_ms_min).
 
 Besides the headline it reports, for the dominant kernel (demod), algorithmic
 bytes per launch (payload samples without CP, x-hat and bits; the channel
@@ -178,6 +181,18 @@ def settle(step, min_ms: float = 200.0, max_ms: float = 3000.0, window: int = 20
         if (spent >= min_ms and prev is not None and abs(cur - prev) <= 0.02 * prev) or spent >= max_ms:
             return spent, steps, cur
         prev = cur
+
+
+def lead_in(step, ms_per_step: float, target_ms: float = 15.0, min_steps: int = 8) -> int:
+    """Untimed steps enqueued after the synchronisation that opens the timed
+    region and before its first event, about target_ms of work at the settled
+    step time.  The GPU idles at that synchronisation; without these steps the
+    first ~40 timed steps ran up to 14 % slower in some runs while its clocks
+    came back.  Returns the number of steps enqueued."""
+    n = max(min_steps, int(target_ms / max(ms_per_step, 1e-3) + 0.5))
+    for _ in range(n):
+        step()
+    return n
 
 
 def copy_peak_gbps(nbytes: int = 1 << 30, reps: int = 10):
@@ -647,8 +662,9 @@ def bench_sweep(args):
 
         for _ in range(args.warmup):
             step()
-        settle(step, min_ms=100.0)
+        _, _, settled = settle(step, min_ms=100.0)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        lead_in(step, settled)
         e0.record()
         for _ in range(args.steps):
             step()
@@ -832,6 +848,7 @@ def main():
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
     ev_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    n_lead = lead_in(step, settle_last)
     for k in range(args.steps):
         step(evs[k])
     ev_end.record()
@@ -937,6 +954,7 @@ def main():
         "events_per_step": 2,
         "warmup_ms": round(settle_ms, 1),
         "warmup_settle_steps": settle_steps,
+        "lead_in_steps": n_lead,
         "estimate_ms": round(est_ms, 5),
         "demod_ms": round(dem_ms, 5),
         "demod_ms_median": round(statistics.median(dem_each), 5),

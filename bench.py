@@ -442,9 +442,11 @@ def bench_denoiser(args):
     print(json.dumps(rec), flush=True)
 
 
-# Integer multiply-adds per CU per clock of the vector ALU (64-wide wavefronts,
-# four SIMDs; the FP32 rate without packed instructions), 256 CUs at 2.4 GHz.
-VALU_INT_MAC_PEAK = 256 * 64 * 2.4e9
+# Integer multiply-adds per second of the vector ALU for the correlation's
+# 2-way 16-bit dot products (v_dot2c_i32_i16: two multiply-adds per lane per
+# instruction at one wave64 instruction per CU per clock, as the other 32-bit
+# vector operations), 256 CUs at 2.4 GHz.
+VALU_INT_MAC_PEAK = 2 * 256 * 64 * 2.4e9
 
 
 def bench_sync(args):

@@ -33,6 +33,8 @@
 namespace rx {
 namespace sync {
 
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+
 constexpr int kThreads = 256;       // threads per metric workgroup
 constexpr int kTile = 4 * kThreads;  // candidates per metric workgroup
 constexpr int kMaxGroups = 64;       // antenna groups (grid.y) at most
@@ -40,10 +42,11 @@ constexpr int kTargetGroups = 2048;  // metric workgroups aimed for (8 per CU)
 constexpr int kRedCand = 64;         // candidates per reduce workgroup (4 threads each)
 
 // Dwords per sample plane of the metric kernel's staging buffer: at least a
-// quarter of the staged samples, and 16 more than a multiple of 64 so the
-// four planes' rows fall in different LDS banks.
+// quarter of the staged samples plus the window words the last step
+// requests ahead (thread 255, window index up to L + 7), and 16 more than a
+// multiple of 64 so the four planes' rows fall in different LDS banks.
 __host__ __device__ constexpr int plane_dwords(int L) {
-  return ((kTile + L + 3 + 3) / 4 + 47) / 64 * 64 + 16;
+  return ((kTile + L + 8 + 3) / 4 + 47) / 64 * 64 + 16;
 }
 
 struct Best {
@@ -78,11 +81,6 @@ __device__ __forceinline__ Best block_best(Best b, Best* sh) {
 // Partial metric of one antenna group for kTile candidates: thread t owns
 // candidates n0 + 4t .. n0 + 4t + 3 and slides a 4-sample register window
 // along the staged samples, so each LDS read feeds 4 (candidate, chip) pairs.
-template <int Q>
-__device__ __forceinline__ void unpack(uint32_t s, int (&re)[Q], int (&im)[Q], int j) {
-  re[j] = (int)(int16_t)(s & 0xFFFFu);
-  im[j] = (int)(int16_t)(s >> 16);
-}
 
 __global__ __launch_bounds__(kThreads) void sync_metric_kernel(const uint32_t* __restrict__ raw, int A, int ag,
                                                                int64_t n_samples, int64_t stride, SyncChips ch,
@@ -104,67 +102,113 @@ __global__ __launch_bounds__(kThreads) void sync_metric_kernel(const uint32_t* _
       ys[(j & 3) * P + (j >> 2)] = i < n_samples ? ya[i] : 0u;
     }
     __syncthreads();
-    int wr[4], wi[4];
+    // Raw sample words in a sliding window: sw0 = samples 4t + m .. + 3,
+    // sw1 = the next four, at the top of the step of chips m .. m + 3.  A
+    // step applies chip pairs (m, m + 1) and (m + 2, m + 3) to the four
+    // candidates with one 2-way 16-bit dot product (exact, into int32) per
+    // candidate and component: re[j] += c_m yr[m + j] + c_(m+1) yr[m + j + 1].
+    // The dot products take the real (imaginary) parts of samples k and k + 1
+    // packed into one word, pr[k - m] (pi[k - m]), built once per k with a
+    // byte permute and kept for the next step (k = m + 4, m + 5 become its
+    // first two).
+    uint32_t sw0[4], sw1[4];
 #pragma unroll
-    for (int j = 0; j < 4; j++) unpack<4>(Y(j), wr, wi, j);
+    for (int u = 0; u < 4; u++) {
+      sw0[u] = Y(u);
+      sw1[u] = Y(u + 4);
+    }
+    auto pre = [](uint32_t lo, uint32_t hi) { return __builtin_amdgcn_perm(hi, lo, 0x05040100u); };
+    auto pim = [](uint32_t lo, uint32_t hi) { return __builtin_amdgcn_perm(hi, lo, 0x07060302u); };
+    uint32_t pr[6], pi[6];
+    pr[0] = pre(sw0[0], sw0[1]);
+    pi[0] = pim(sw0[0], sw0[1]);
+    pr[1] = pre(sw0[1], sw0[2]);
+    pi[1] = pim(sw0[1], sw0[2]);
     int re[4] = {0, 0, 0, 0}, im[4] = {0, 0, 0, 0};
-    // window slot (m + j) % 4 holds sample 4t + m + j
-    // Steps of four chips, software-pipelined: the next step's chips (one
-    // dword, little-endian bytes) and window samples are requested once this
-    // step has taken its own, so the wait for them (one counter for scalar and
-    // LDS loads) falls a whole step after they were issued.
     int m = 0;
-    if (L >= 4) {
-      int cn;
-      uint32_t yn[4];
-      __builtin_memcpy(&cn, ch.c, 4);
+    // Steps of four chips (one little-endian dword of them), software-
+    // pipelined: the next step's chips and samples are requested once this
+    // step has taken its own, so the wait for them falls a whole step after
+    // they were issued.  The samples are requested on every step, also ahead
+    // of a tail of 1..3 chips or of nothing (window indices up to L + 7,
+    // inside the staging planes; those past the staged span are never used).
+    int cn = 0;
+    if (L >= 4) __builtin_memcpy(&cn, ch.c, 4);
+    // One step of chips m .. m + 3 over the window words a (samples m ..),
+    // b (m + 4 ..); requests the next four into n.
+    auto step = [&](int mm, uint32_t (&a)[4], uint32_t (&b)[4], uint32_t (&n)[4]) {
+      const int cw = cn;
+      __builtin_amdgcn_sched_barrier(0);
+      if (mm + 8 <= L) __builtin_memcpy(&cn, ch.c + mm + 4, 4);
 #pragma unroll
-      for (int u = 0; u < 4; u++) yn[u] = Y(u + 4);
-      for (; m + 4 <= L; m += 4) {
-        const int cw = cn;
-        uint32_t yc[4];
+      for (int u = 0; u < 4; u++) n[u] = Y(mm + u + 8);  // window index <= L + 7
+      pr[2] = pre(a[2], a[3]);
+      pi[2] = pim(a[2], a[3]);
+      pr[3] = pre(a[3], b[0]);
+      pi[3] = pim(a[3], b[0]);
+      pr[4] = pre(b[0], b[1]);
+      pi[4] = pim(b[0], b[1]);
+      pr[5] = pre(b[1], b[2]);
+      pi[5] = pim(b[1], b[2]);
+      // chips mm .. mm + 3 as two pairs of int16
+      const s16x2 c01 = {(short)(int8_t)(uint32_t)cw, (short)(int8_t)((uint32_t)cw >> 8)};
+      const s16x2 c23 = {(short)(int8_t)((uint32_t)cw >> 16), (short)(int8_t)((uint32_t)cw >> 24)};
 #pragma unroll
-        for (int u = 0; u < 4; u++) yc[u] = yn[u];
-        __builtin_amdgcn_sched_barrier(0);
-        if (m + 8 <= L) {
-          __builtin_memcpy(&cn, ch.c + m + 4, 4);
+      for (int j = 0; j < 4; j++) {
+        re[j] = __builtin_amdgcn_sdot2(__builtin_bit_cast(s16x2, pr[j]), c01, re[j], false);
+        im[j] = __builtin_amdgcn_sdot2(__builtin_bit_cast(s16x2, pi[j]), c01, im[j], false);
+      }
 #pragma unroll
-          for (int u = 0; u < 4; u++) yn[u] = Y(m + u + 8);
+      for (int j = 0; j < 4; j++) {
+        re[j] = __builtin_amdgcn_sdot2(__builtin_bit_cast(s16x2, pr[j + 2]), c23, re[j], false);
+        im[j] = __builtin_amdgcn_sdot2(__builtin_bit_cast(s16x2, pi[j + 2]), c23, im[j], false);
+      }
+      pr[0] = pr[4];
+      pi[0] = pi[4];
+      pr[1] = pr[5];
+      pi[1] = pi[5];
+    };
+    // Three steps per iteration, the three window buffers taking turns (the
+    // roles cycle with period three, so no register copies), then at most
+    // two more steps; the tail reads the window from sw0, sw1.
+    uint32_t sw2[4];
+    for (; m + 12 <= L; m += 12) {
+      step(m, sw0, sw1, sw2);
+      step(m + 4, sw1, sw2, sw0);
+      step(m + 8, sw2, sw0, sw1);
+    }
+    if (m + 4 <= L) {
+      step(m, sw0, sw1, sw2);
+      m += 4;
+      if (m + 4 <= L) {
+        step(m, sw1, sw2, sw0);
+        m += 4;
+#pragma unroll
+        for (int u = 0; u < 4; u++) {  // window: sw2, sw0
+          sw1[u] = sw0[u];
+          sw0[u] = sw2[u];
         }
+      } else {
 #pragma unroll
-        for (int u = 0; u < 4; u++) {
-          const int c = (int)(int8_t)(uint32_t)(cw >> (8 * u));  // chip m + u
-#pragma unroll
-          for (int j = 0; j < 4; j++) {
-            // 24-bit products (samples are 16-bit, chips 8-bit): exact, and a
-            // full-rate multiply-add instead of a 32-bit integer multiply
-            re[j] += __mul24(c, wr[(u + j) & 3]);
-            im[j] += __mul24(c, wi[(u + j) & 3]);
-          }
-          unpack<4>(yc[u], wr, wi, u);  // slot u now holds sample 4t + m + u + 4
+        for (int u = 0; u < 4; u++) {  // window: sw1, sw2
+          sw0[u] = sw1[u];
+          sw1[u] = sw2[u];
         }
       }
     }
-    for (; m < L; m++) {  // tail: rotate by hand
-      const int c = ch.c[m];
+    // tail of L mod 4 chips: chip m + e meets sample m + e + j, which is
+    // window word e + j (sw0, then sw1)
 #pragma unroll
-      for (int j = 0; j < 4; j++) {
-        const int s = (m + j) & 3;
-        int vr = wr[0], vi = wi[0];
+    for (int e = 0; e < 3; e++) {
+      if (m + e < L) {
+        const int c = ch.c[m + e];
 #pragma unroll
-        for (int k = 1; k < 4; k++)
-          if (s == k) {
-            vr = wr[k];
-            vi = wi[k];
-          }
-        re[j] += __mul24(c, vr);
-        im[j] += __mul24(c, vi);
+        for (int j = 0; j < 4; j++) {
+          const uint32_t w = (e + j) < 4 ? sw0[(e + j) & 3] : sw1[(e + j) & 3];
+          re[j] += __mul24(c, (int)(int16_t)(w & 0xFFFFu));
+          im[j] += __mul24(c, (int)(int16_t)(w >> 16));
+        }
       }
-      const int s = m & 3;
-      const uint32_t nx = Y(m + 4);
-#pragma unroll
-      for (int k = 0; k < 4; k++)
-        if (s == k) unpack<4>(nx, wr, wi, k);
     }
 #pragma unroll
     for (int j = 0; j < 4; j++) acc[j] += (uint64_t)((int64_t)re[j] * re[j]) + (uint64_t)((int64_t)im[j] * im[j]);

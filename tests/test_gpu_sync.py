@@ -50,6 +50,17 @@ def test_metric_matches_oracle_on_random_streams(rx, A, n, stride, n_search, L):
     _check_find(rx, raw, pn, n_search, n_samples=n)
 
 
+@pytest.mark.parametrize("L", [2, 3, 4, 5, 6, 8, 9, 10, 11, 12, 13, 16, 18, 20, 23, 24, 29, 44, 1021, 1024])
+def test_metric_every_chip_count_path(rx, L):
+    # chip lengths covering each way the correlation loop ends: whole groups of
+    # twelve chips, one or two further steps of four, and a tail of 0..3 chips
+    _say("sync metric chips", L)
+    rng = np.random.default_rng(7000 + L)
+    raw = rng.integers(-32768, 32768, size=(3, 1200 + L, 2)).astype(np.int16)
+    pn = rng.choice([-1, 0, 1], size=L)
+    _check_find(rx, raw, pn, 1100, n_samples=1180 + L)
+
+
 def test_full_scale_extremes_stay_exact(rx):
     pn = pn_sequence()
     raw = np.full((8, 800, 2), -32768, dtype=np.int16)

@@ -16,7 +16,7 @@
 // the window's reads (thread t, sample 4t + m) are consecutive across lanes
 // with compile-time offsets instead of a 4-dword stride (4-way LDS bank
 // conflicts).  The per-group partial metrics are summed by sync_reduce_kernel
-// (integer sums: exact in any order, 4 threads per candidate), which also
+// (integer sums: exact in any order, 16 threads per candidate), which also
 // reduces each 64 candidates to the best (M, n); sync_argmax_kernel reduces
 // those in one workgroup.
 // "Best" = larger M, then smaller n: a total order, so the result does not
@@ -39,7 +39,8 @@ constexpr int kThreads = 256;       // threads per metric workgroup
 constexpr int kTile = 4 * kThreads;  // candidates per metric workgroup
 constexpr int kMaxGroups = 64;       // antenna groups (grid.y) at most
 constexpr int kTargetGroups = 2048;  // metric workgroups aimed for (8 per CU)
-constexpr int kRedCand = 64;         // candidates per reduce workgroup (4 threads each)
+constexpr int kRedCand = 64;         // candidates per reduce workgroup
+constexpr int kRedWaves = 16;        // wavefronts per reduce workgroup (threads per candidate)
 
 // Dwords per sample plane of the metric kernel's staging buffer: at least a
 // quarter of the staged samples plus the window words the last step
@@ -221,23 +222,26 @@ __global__ __launch_bounds__(kThreads) void sync_metric_kernel(const uint32_t* _
   }
 }
 
-// M[n] = sum over antenna groups (integers: any order is exact), 4 threads
-// per candidate (wave w sums groups w, w + 4, ...), plus the best (M, n) of
-// each workgroup's kRedCand candidates.
-__global__ __launch_bounds__(256) void sync_reduce_kernel(const uint64_t* __restrict__ part, int G, int64_t n_search,
-                                                          uint64_t* __restrict__ M, uint64_t* __restrict__ cand_v,
-                                                          int64_t* __restrict__ cand_i) {
-  __shared__ uint64_t sums[4][kRedCand];
+// M[n] = sum over antenna groups (integers: any order is exact), kRedWaves
+// threads per candidate (wave w sums groups w, w + kRedWaves, ...: at most
+// four loads each, so the partial metrics stream with many loads in flight),
+// plus the best (M, n) of each workgroup's kRedCand candidates.
+__global__ __launch_bounds__(64 * kRedWaves) void sync_reduce_kernel(const uint64_t* __restrict__ part, int G,
+                                                                     int64_t n_search, uint64_t* __restrict__ M,
+                                                                     uint64_t* __restrict__ cand_v,
+                                                                     int64_t* __restrict__ cand_i) {
+  __shared__ uint64_t sums[kRedWaves][kRedCand];
   const int c = threadIdx.x & (kRedCand - 1), w = threadIdx.x / kRedCand;
   const int64_t n = (int64_t)blockIdx.x * kRedCand + c;
   const bool ok = n < n_search;
   uint64_t v = 0;
   if (ok)
-    for (int g = w; g < G; g += 4) v += part[(int64_t)g * n_search + n];
+    for (int g = w; g < G; g += kRedWaves) v += part[(int64_t)g * n_search + n];
   sums[w][c] = v;
   __syncthreads();
   if (w == 0) {
-    v += sums[1][c] + sums[2][c] + sums[3][c];
+#pragma unroll
+    for (int k = 1; k < kRedWaves; k++) v += sums[k][c];
     if (ok && M) M[n] = v;
     Best b = {ok ? v : 0ull, ok ? n : INT64_MAX};
 #pragma unroll
@@ -318,7 +322,8 @@ hipError_t sync_find(const uint32_t* raw, int A, int64_t n_samples, int64_t stri
                      raw, A, ag, n_samples, stride, ch, n_search, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(sync::sync_reduce_kernel, dim3((unsigned)nb), dim3(256), 0, st, (const uint64_t*)part, G,
+  hipLaunchKernelGGL(sync::sync_reduce_kernel, dim3((unsigned)nb), dim3(64 * sync::kRedWaves), 0, st,
+                     (const uint64_t*)part, G,
                      n_search, M, cv, ci);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(sync::sync_argmax_kernel, dim3(1), dim3(256), 0, st, (const uint64_t*)cv, (const int64_t*)ci,

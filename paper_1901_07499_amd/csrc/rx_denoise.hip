@@ -135,19 +135,11 @@ __device__ __forceinline__ void unit32(const bfbits* __restrict__ X, int row0, c
   }
 }
 
-// The two halves of unit32, for software pipelining: the 7 tap operands of a
-// unit, then its 14 products.
+// The 7 tap operands of a unit (the loads of unit32, apart from its products).
 __device__ __forceinline__ void unit32_load(const bfbits* __restrict__ X, int row0, bf16x8 (&b)[7]) {
   const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
 #pragma unroll
   for (int k = 0; k < 7; k++) b[k] = as_bf16x8(*reinterpret_cast<const uint4*>(X + (row0 + k + r) * RS + 8 * q));
-}
-__device__ __forceinline__ void unit32_mma(const bf16x8 (&b)[7], const bf16x8 (&w)[2][7], f32x4 (&acc)[2]) {
-#pragma unroll
-  for (int k = 0; k < 7; k++) {
-    acc[0] = mfma(w[0][k], b[k], acc[0]);
-    acc[1] = mfma(w[1][k], b[k], acc[1]);
-  }
 }
 
 // Four dwords at dword index i of an LDS buffer of 2-channel positions
@@ -233,28 +225,40 @@ __device__ __forceinline__ void bias_init(f32x4 (&acc)[2], const float* __restri
     for (int i = 0; i < 4; i++) acc[h][i] = b[16 * h + 4 * q + i];
 }
 
-// A 32-input-channel layer of an inference tile: this wavefront's units
-// u = wave, wave + 4, ... (NU in all, a multiple of 4), with the next unit's
-// tap operands requested before the current unit's products so the LDS
-// latency overlaps the MFMAs.  Unit u covers LDS rows first + 16 u + r of the
-// output, reading rows from first + 16 u - 3; positions p0 + 16 u + r.
+// A 32-input-channel layer of an inference tile, two units at a time: the
+// wavefront's units u = wave + 4 j (NU in all per layer, a multiple of 8)
+// are taken in pairs (j, j + 1), whose 14 tap operands are requested
+// together and whose products run as four interleaved accumulation chains
+// (each product waits on the one four places back instead of two).  Unit u
+// covers LDS rows first + 16 u + r of the output, reading rows from
+// first + 16 u - 3; positions p0 + 16 u + r.  One unit at a time with the
+// next unit's operands requested ahead (the same registers) ran 2 % slower.
 template <int NU>
-__device__ __forceinline__ void layer32_pipelined(const bfbits* __restrict__ X, bfbits* __restrict__ Y, int first,
-                                                  int p0, int U, const bf16x8 (&w)[2][7],
-                                                  const float* __restrict__ bias) {
-  static_assert(NU % 4 == 0, "whole rounds of the 4 wavefronts");
+__device__ __forceinline__ void layer32_paired(const bfbits* __restrict__ X, bfbits* __restrict__ Y, int first,
+                                               int p0, int U, const bf16x8 (&w)[2][7],
+                                               const float* __restrict__ bias) {
+  static_assert(NU % 8 == 0, "pairs of whole rounds of the 4 wavefronts");
   const int wave = threadIdx.x >> 6, r = threadIdx.x & 15;
-  bf16x8 b[2][7];
-  unit32_load(X, first + 16 * wave - 3, b[0]);
 #pragma unroll
-  for (int j = 0; j < NU / 4; j++) {
-    const int u = wave + 4 * j;
-    if (j + 1 < NU / 4) unit32_load(X, first + 16 * (u + 4) - 3, b[(j + 1) & 1]);
-    f32x4 acc[2];
-    bias_init(acc, bias);
-    unit32_mma(b[j & 1], w, acc);
-    relu_unit(acc, p0 + 16 * u, U);
-    store_unit(Y, first + 16 * u + r, acc);
+  for (int j = 0; j < NU / 4; j += 2) {
+    const int u0 = wave + 4 * j, u1 = u0 + 4;
+    bf16x8 b0[7], b1[7];
+    unit32_load(X, first + 16 * u0 - 3, b0);
+    unit32_load(X, first + 16 * u1 - 3, b1);
+    f32x4 a0[2], a1[2];
+    bias_init(a0, bias);
+    bias_init(a1, bias);
+#pragma unroll
+    for (int k = 0; k < 7; k++) {
+      a0[0] = mfma(w[0][k], b0[k], a0[0]);
+      a1[0] = mfma(w[0][k], b1[k], a1[0]);
+      a0[1] = mfma(w[1][k], b0[k], a0[1]);
+      a1[1] = mfma(w[1][k], b1[k], a1[1]);
+    }
+    relu_unit(a0, p0 + 16 * u0, U);
+    store_unit(Y, first + 16 * u0 + r, a0);
+    relu_unit(a1, p0 + 16 * u1, U);
+    store_unit(Y, first + 16 * u1 + r, a1);
   }
 }
 
@@ -356,7 +360,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
       __syncthreads();
       if (TRAIN) store_masks(XA, t0, U, io.M1 + row * UP);
       // layer 2: A -> B
-      if constexpr (!TRAIN) layer32_pipelined<U2>(XA, XB, 6, t0 - 6, U, w2, b2);
+      if constexpr (!TRAIN) layer32_paired<U2>(XA, XB, 6, t0 - 6, U, w2, b2);
       else for (int u = wave; u < U2; u += 4) {
         const int idx = 6 + 16 * u + r;
         const int p = t0 - 6 + 16 * u + r;
@@ -371,7 +375,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
       __syncthreads();
       if (TRAIN) store_masks(XB, t0, U, io.M2 + row * UP);
       // layer 3: B -> A
-      if constexpr (!TRAIN) layer32_pipelined<U3>(XB, XA, 9, t0 - 3, U, w3, b3);
+      if constexpr (!TRAIN) layer32_paired<U3>(XB, XA, 9, t0 - 3, U, w3, b3);
       else for (int u = wave; u < U3; u += 4) {
         const int idx = 9 + 16 * u + r;
         const int p = t0 - 3 + 16 * u + r;
